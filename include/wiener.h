@@ -1,0 +1,265 @@
+/*
+ * wiener.h -- C ABI of the MI355X Wiener-reconstruction library.
+ *
+ * The library computes the mean of the Wiener filter in its signal-space form
+ * (eq:WF, Sec. 3.3.1 of Kitaura et al., "Cosmic cartography of the large-scale
+ * structure with SDSS DR6"):
+ *
+ *     s = (S^-1 + W^T N^-1 W)^-1 W^T N^-1 delta^o
+ *
+ * on a periodic n^3 grid of side L, with
+ *   - W = diag(w), the 3D completeness (Sec. 3.1.3; response of eq:RO with no
+ *     bias or redshift-space operator),
+ *   - N = diag(w / nbar), the LSQ shot-noise covariance (eq:noiseav),
+ *   - delta^o = n^o / nbar - w, the observed overdensity (eq:datamodel), with
+ *     nbar = N_gal / sum(w) (eq:nmean, per cell),
+ *   - S diagonal in Fourier space with eigenvalues P(k)/dV (Sec. 3.3.1),
+ *   - n^o the galaxy field gridded by mass assignment on the comb of
+ *     def:ngrid (Sec. 3.1.2), optionally 2x supersampled and low-passed.
+ * Multiplying by nbar, the library solves the SPD system
+ *
+ *     A s = b,  A = F^-1 diag(Lambda) F + diag(nbar w),
+ *     Lambda_m = dV / P(k_m) (m != 0), Lambda_0 = 0,
+ *     b = n^o - nbar w on cells with w > 0, 0 elsewhere,
+ *
+ * by conjugate gradients (the "iterative Krylov-space inversion" of Sec. 1),
+ * in FP64 or in mixed precision (FP32 operator inside an FP64 iterative
+ * refinement loop).
+ *
+ * Conventions (all entry points):
+ *   - Every call returns a wf_status.  wf_last_error() gives a message for the
+ *     most recent failing call on that context.  No exception or abort crosses
+ *     the ABI.
+ *   - Grid arrays are C-order [x][y][z] with z contiguous, n^3 doubles; grid
+ *     nodes sit at x = i * L / n, i in [0, n).
+ *   - A pointer argument carries a wf_mem tag saying whether it is host memory
+ *     or device memory on the context's GPU.  With WF_HOST the call has
+ *     finished using the buffer when it returns.  With WF_DEVICE the work is
+ *     ordered on the context's stream (results are valid once that stream has
+ *     reached the call) -- except where a call documents that it synchronises.
+ *   - The library never keeps a caller pointer after a call returns; inputs are
+ *     copied.  Outputs are written only on WF_OK (and for WF_ENOTCONV, see
+ *     wf_solve).  Device memory is obtained through the allocator callbacks
+ *     given at context creation (NULL callbacks: hipMalloc / hipFree).
+ *   - One context per host thread at a time.  Different contexts are
+ *     independent.
+ */
+#ifndef WIENER_H
+#define WIENER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WF_ABI_VERSION 1
+
+typedef enum {
+  WF_OK = 0,
+  WF_EINVAL = 1,      /* an argument is out of range, non-finite or malformed */
+  WF_ESTATE = 2,      /* calls made out of order (e.g. solve before data)     */
+  WF_ENOMEM = 3,      /* device allocation failed / footprint over budget     */
+  WF_EDEVICE = 4,     /* a HIP runtime call failed                            */
+  WF_ENOTCONV = 5,    /* max_iter reached before the tolerance                */
+  WF_EOVERFLOW = 6,   /* too many galaxies for exact integer accumulation     */
+  WF_EBREAKDOWN = 7   /* p.Ap <= 0 or non-finite: operator not SPD            */
+} wf_status;
+
+typedef enum { WF_HOST = 0, WF_DEVICE = 1 } wf_mem;
+
+/* Mass-assignment kernels named in Sec. 3.1.2. */
+typedef enum { WF_NGP = 0, WF_CIC = 1, WF_TSC = 2 } wf_scheme;
+
+typedef enum {
+  WF_FP64 = 0,   /* FP64 vectors, FFTs and reductions                          */
+  WF_MIXED = 1   /* FP32 inner CG (FP64 dots) inside FP64 iterative refinement */
+} wf_precision;
+
+/* Device allocator callbacks (e.g. a framework's caching allocator).  alloc
+ * returns device memory of at least `bytes` on the context's device, aligned
+ * to 256 bytes, or NULL. */
+typedef void* (*wf_alloc_fn)(size_t bytes, void* user);
+typedef void (*wf_free_fn)(void* dptr, void* user);
+
+typedef struct wf_ctx wf_ctx;
+typedef struct wf_server wf_server;
+
+/* Solver options.
+ *   tol         stop when ||b - A x|| / ||b|| <= tol.  FP64: on the recursive
+ *               CG residual.  MIXED: on the FP64 residual recomputed after
+ *               each refinement step.  tol = 0 runs exactly max_iter CG
+ *               iterations (FP64).
+ *   max_iter    FP64: CG iterations.  MIXED: total inner iterations.
+ *   inner_tol   MIXED only: relative residual reduction of each inner FP32 CG
+ *               solve (e.g. 1e-4).  0 selects the default.
+ *   max_outer   MIXED only: refinement steps (0 selects the default, 16).
+ *   check_every host convergence checks every this many iterations (0: 16).
+ *               Results do not depend on it: the device stops iterating at
+ *               convergence by itself. */
+typedef struct {
+  wf_precision precision;
+  double tol;
+  int32_t max_iter;
+  double inner_tol;
+  int32_t max_outer;
+  int32_t check_every;
+} wf_solve_opts;
+
+typedef struct {
+  int32_t iters_total;        /* CG iterations (MIXED: sum of inner)          */
+  int32_t outer_steps;        /* MIXED refinement steps (FP64: 0)             */
+  double rel_res_recursive;   /* last recursive residual of the (inner) CG    */
+  double rel_res_true;        /* ||b - A x|| / ||b|| with the FP64 operator   */
+  double time_ms;             /* wall time of the solve on the device         */
+  double model_bytes;         /* algorithmic HBM bytes moved by the solve     */
+  double nbar;                /* mean density per cell used                   */
+  int32_t status;             /* wf_status of the solve                       */
+} wf_solve_info;
+
+/* ---- library ----------------------------------------------------------- */
+int wf_abi_version(void);
+const char* wf_status_str(wf_status s);
+
+/* ---- context ----------------------------------------------------------- */
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * owned by the caller (NULL: the null stream).  alloc/free may be NULL. */
+wf_status wf_ctx_create(wf_ctx** out, int device, void* hip_stream,
+                        wf_alloc_fn alloc, wf_free_fn free_fn, void* user);
+wf_status wf_ctx_destroy(wf_ctx* ctx);
+const char* wf_last_error(const wf_ctx* ctx);
+
+/* Grid: n cells per axis, n = 2^a 3^b with b <= 1 and 8 <= n <= 512; box side
+ * L > 0 in Mpc.  Resets every other input of the context. */
+wf_status wf_set_grid(wf_ctx* ctx, int32_t n, double box_mpc);
+
+/* 3D completeness w (Sec. 3.1.3, "w <= 1"): n^3 doubles, finite, 0 <= w <= 1,
+ * not all zero; otherwise WF_EINVAL.  Synchronises. */
+wf_status wf_set_mask(wf_ctx* ctx, const double* w, wf_mem mem);
+
+/* Prior spectrum sampled on the |m|^2 lattice: p_by_m2[j] = P(k) in Mpc^3 at
+ * k = 2 pi sqrt(j) / L, j = 0 .. 3 (n/2)^2 (len must equal that count).  Entry
+ * 0 is ignored (Lambda_0 = 0); the others must be finite and > 0, else
+ * WF_EINVAL.  Synchronises. */
+wf_status wf_set_power(wf_ctx* ctx, const double* p_by_m2, int64_t len,
+                       wf_mem mem);
+
+/* Galaxy positions (Sec. 3.1.2 point-source field): xyz[n_gal][3] in Mpc with
+ * 0 <= x < L on every axis (else WF_EINVAL); n_gal < 2^24 (else WF_EOVERFLOW,
+ * the bound for exact int64 accumulation).  n_gal = 0 is allowed.
+ * Synchronises. */
+wf_status wf_set_galaxies(wf_ctx* ctx, const double* xyz, int64_t n_gal,
+                          wf_mem mem);
+
+/* Gridding (Sec. 3.1.2, def:ngrid): fixed-point mass assignment onto the
+ * (supersample * n)^3 grid with exact int64 accumulation (weights in units of
+ * 2^-39 for CIC/TSC, counts for NGP), then for supersample = 2 the ideal
+ * low-pass (|m| < n/2 on every axis, Nyquist planes dropped) and resampling at
+ * n^3; then nbar = N_gal / sum(w) and b.  Needs grid, mask and galaxies. */
+wf_status wf_deposit(wf_ctx* ctx, wf_scheme scheme, int32_t supersample);
+
+/* Copies out the last deposit: the integer (s n)^3 grid, n^o (n^3 doubles)
+ * and nbar.  Any output may be NULL.  Synchronises. */
+wf_status wf_get_deposit(wf_ctx* ctx, int64_t* fine_counts, double* n_obs,
+                         double* nbar_cell, wf_mem mem);
+
+/* Test hook: replaces the data vector by b (n^3) and nbar (> 0). */
+wf_status wf_set_rhs(wf_ctx* ctx, const double* b, double nbar_cell,
+                     wf_mem mem);
+
+/* Test hook: Av = A v with the operator in the given precision (MIXED: the
+ * FP32 operator on v rounded to FP32, result widened).  Needs grid, mask,
+ * power and nbar (from wf_deposit or wf_set_rhs). */
+wf_status wf_apply_operator(wf_ctx* ctx, wf_precision prec, const double* v,
+                            double* Av, wf_mem mem);
+
+/* Test hook: the unnormalised forward real-to-complex 3D DFT of v (n^3) in
+ * numpy.fft.rfftn layout: spec[n][n][n/2+1] complex as interleaved doubles. */
+wf_status wf_forward_spectrum(wf_ctx* ctx, wf_precision prec, const double* v,
+                              double* spec, wf_mem mem);
+
+/* Solves A s = b (see the top of this file) from s = 0 and writes s (n^3).
+ * WF_ENOTCONV: tolerance not reached within max_iter; s_out holds the last
+ * iterate and info is filled.  WF_EBREAKDOWN: s_out untouched.  info may be
+ * NULL.  Synchronises. */
+wf_status wf_solve(wf_ctx* ctx, const wf_solve_opts* opts, double* s_out,
+                   wf_mem mem, wf_solve_info* info);
+
+/* Krylov state of an FP64 solve, for checkpoint / resume.  wf_solve_begin
+ * starts an FP64 solve, wf_solve_step runs up to `iters` iterations,
+ * wf_solve_snapshot copies the state (x, r, p and scalars) into host_buf of
+ * wf_snapshot_bytes() bytes, wf_solve_resume restores it into a context with
+ * the same grid, mask, power and rhs, and wf_solve_finish writes s and info.
+ * Continuing from a snapshot gives bit-identical results. */
+wf_status wf_solve_begin(wf_ctx* ctx, const wf_solve_opts* opts);
+wf_status wf_solve_step(wf_ctx* ctx, int32_t iters, int32_t* done);
+size_t wf_snapshot_bytes(const wf_ctx* ctx);
+wf_status wf_solve_snapshot(wf_ctx* ctx, void* host_buf, size_t bytes);
+wf_status wf_solve_resume(wf_ctx* ctx, const void* host_buf, size_t bytes);
+wf_status wf_solve_finish(wf_ctx* ctx, double* s_out, wf_mem mem,
+                          wf_solve_info* info);
+
+/* Multi-RHS solve: nrhs catalogues on the context's grid, mask and power,
+ * each deposited (scheme, supersample) and solved in MIXED or FP64 precision
+ * with batched kernels (one launch per pass covers every RHS).  xyz[i] holds
+ * n_gal[i] galaxies (same rules as wf_set_galaxies); s_out[i] receives n^3
+ * doubles; infos[i] (may be NULL) the per-RHS info.  Returns the worst status.
+ * Synchronises. */
+wf_status wf_solve_batch(wf_ctx* ctx, int32_t nrhs, const double* const* xyz,
+                         const int64_t* n_gal, wf_scheme scheme,
+                         int32_t supersample, const wf_solve_opts* opts,
+                         double* const* s_out, wf_mem mem,
+                         wf_solve_info* infos);
+
+/* Device bytes one solve needs at the peak of its phases (deposit or solve). */
+size_t wf_footprint_bytes(int32_t n, int32_t supersample, wf_precision prec,
+                          int32_t nrhs);
+
+/* ---- serving ----------------------------------------------------------- */
+/* A reconstruction request: all pointers are host memory, copied at submit. */
+typedef struct {
+  int32_t n;
+  double box_mpc;
+  const double* w;          /* n^3 */
+  const double* p_by_m2;    /* 3 (n/2)^2 + 1 */
+  const double* xyz;        /* [n_gal][3] */
+  int64_t n_gal;
+  wf_scheme scheme;
+  int32_t supersample;
+  wf_solve_opts opts;
+} wf_request;
+
+typedef struct {
+  int64_t completed;
+  int64_t failed;
+  double solves_per_s;      /* completed / (last completion - first arrival) */
+  double p50_ms, p99_ms;    /* submit -> result ready on the host            */
+  size_t peak_bytes;        /* peak device bytes held by admitted requests   */
+} wf_server_stats;
+
+/* A continuous-batching server on one device.  Requests are admitted while
+ * the sum of their footprints stays within hbm_budget bytes and at most
+ * max_active run; admitted requests keep their Krylov state on the device and
+ * advance together (requests of equal n share batched launches).
+ * wf_server_submit returns WF_ENOMEM if the request can never fit. */
+wf_status wf_server_create(wf_server** out, int device, size_t hbm_budget,
+                           int32_t max_active, wf_alloc_fn alloc,
+                           wf_free_fn free_fn, void* user);
+wf_status wf_server_submit(wf_server* srv, const wf_request* req,
+                           uint64_t* ticket);
+/* done = 1 once the result is ready (info filled, may be NULL). */
+wf_status wf_server_poll(wf_server* srv, uint64_t ticket, int32_t* done,
+                         wf_solve_info* info);
+/* Copies the result (n^3 doubles, host) and releases the ticket. */
+wf_status wf_server_fetch(wf_server* srv, uint64_t ticket, double* s_out);
+wf_status wf_server_cancel(wf_server* srv, uint64_t ticket);
+wf_status wf_server_stats_get(wf_server* srv, wf_server_stats* stats);
+const char* wf_server_last_error(const wf_server* srv);
+wf_status wf_server_destroy(wf_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WIENER_H */

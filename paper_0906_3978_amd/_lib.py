@@ -1,0 +1,342 @@
+"""ctypes binding of libwiener.so (include/wiener.h).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+library.  numpy arrays are passed as host memory (WF_HOST); torch tensors on
+the GPU as device memory (WF_DEVICE).  PyTorch supplies the device allocator
+(its caching allocator, through the ABI's callbacks) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwiener.so")
+
+WF_OK, WF_EINVAL, WF_ESTATE, WF_ENOMEM, WF_EDEVICE, WF_ENOTCONV, WF_EOVERFLOW, WF_EBREAKDOWN = range(8)
+STATUS_NAMES = ["WF_OK", "WF_EINVAL", "WF_ESTATE", "WF_ENOMEM", "WF_EDEVICE", "WF_ENOTCONV",
+                "WF_EOVERFLOW", "WF_EBREAKDOWN"]
+WF_HOST, WF_DEVICE = 0, 1
+SCHEMES = {"ngp": 0, "cic": 1, "tsc": 2}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters_total", C.c_int32), ("outer_steps", C.c_int32),
+                ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double),
+                ("time_ms", C.c_double), ("model_bytes", C.c_double), ("nbar", C.c_double),
+                ("status", C.c_int32)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["status_name"] = STATUS_NAMES[self.status] if 0 <= self.status < 8 else str(self.status)
+        return d
+
+
+class Request(C.Structure):
+    _fields_ = [("n", C.c_int32), ("box_mpc", C.c_double), ("w", C.c_void_p),
+                ("p_by_m2", C.c_void_p), ("xyz", C.c_void_p), ("n_gal", C.c_int64),
+                ("scheme", C.c_int), ("supersample", C.c_int32), ("opts", SolveOpts)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("solves_per_s", C.c_double),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("peak_bytes", C.c_size_t)]
+
+
+class WienerError(RuntimeError):
+    def __init__(self, code, msg):
+        self.code = code
+        name = STATUS_NAMES[code] if 0 <= code < 8 else str(code)
+        super().__init__(f"{name}: {msg}")
+
+
+_LIB = None
+
+# name -> (restype, argtypes)
+_V, _P, _I32, _I64, _D, _SZ = C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+SIGNATURES = {
+    "wf_abi_version": (C.c_int, []),
+    "wf_status_str": (C.c_char_p, [C.c_int]),
+    "wf_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, _V, ALLOC_FN, FREE_FN, _V]),
+    "wf_ctx_destroy": (C.c_int, [_V]),
+    "wf_last_error": (C.c_char_p, [_V]),
+    "wf_set_grid": (C.c_int, [_V, _I32, _D]),
+    "wf_set_mask": (C.c_int, [_V, _P, C.c_int]),
+    "wf_set_power": (C.c_int, [_V, _P, _I64, C.c_int]),
+    "wf_set_galaxies": (C.c_int, [_V, _P, _I64, C.c_int]),
+    "wf_deposit": (C.c_int, [_V, C.c_int, _I32]),
+    "wf_get_deposit": (C.c_int, [_V, _P, _P, _P, C.c_int]),
+    "wf_set_rhs": (C.c_int, [_V, _P, _D, C.c_int]),
+    "wf_apply_operator": (C.c_int, [_V, C.c_int, _P, _P, C.c_int]),
+    "wf_forward_spectrum": (C.c_int, [_V, C.c_int, _P, _P, C.c_int]),
+    "wf_solve": (C.c_int, [_V, C.POINTER(SolveOpts), _P, C.c_int, C.POINTER(SolveInfo)]),
+    "wf_solve_begin": (C.c_int, [_V, C.POINTER(SolveOpts)]),
+    "wf_solve_step": (C.c_int, [_V, _I32, C.POINTER(C.c_int32)]),
+    "wf_snapshot_bytes": (_SZ, [_V]),
+    "wf_solve_snapshot": (C.c_int, [_V, _P, _SZ]),
+    "wf_solve_resume": (C.c_int, [_V, _P, _SZ]),
+    "wf_solve_finish": (C.c_int, [_V, _P, C.c_int, C.POINTER(SolveInfo)]),
+    "wf_solve_batch": (C.c_int, [_V, _I32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_int,
+                                 _I32, C.POINTER(SolveOpts), C.POINTER(C.c_void_p), C.c_int,
+                                 C.POINTER(SolveInfo)]),
+    "wf_footprint_bytes": (_SZ, [_I32, _I32, C.c_int, _I32]),
+    "wf_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, _SZ, _I32, ALLOC_FN, FREE_FN, _V]),
+    "wf_server_submit": (C.c_int, [_V, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "wf_server_poll": (C.c_int, [_V, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(SolveInfo)]),
+    "wf_server_fetch": (C.c_int, [_V, C.c_uint64, _P]),
+    "wf_server_cancel": (C.c_int, [_V, C.c_uint64]),
+    "wf_server_stats_get": (C.c_int, [_V, C.POINTER(ServerStats)]),
+    "wf_server_last_error": (C.c_char_p, [_V]),
+    "wf_server_destroy": (C.c_int, [_V]),
+}
+
+
+def lib():
+    """Loads libwiener.so; raises if it has not been built (no fallback)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_0906_3978_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a):
+    """(pointer, mem) of a numpy array (host) or a torch GPU tensor (device)."""
+    if a is None:
+        return None, WF_HOST
+    if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("arrays must be C-contiguous")
+        return a.ctypes.data, WF_HOST
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        if not a.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return a.data_ptr(), (WF_DEVICE if a.is_cuda else WF_HOST)
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _torch_allocator(device):
+    import torch
+
+    def alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        except Exception:  # out of memory: the library reports WF_ENOMEM
+            return None
+
+    def free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return ALLOC_FN(alloc), FREE_FN(free)
+
+
+@dataclass
+class Info:
+    iters_total: int
+    outer_steps: int
+    rel_res_recursive: float
+    rel_res_true: float
+    time_ms: float
+    model_bytes: float
+    nbar: float
+    status: int
+    status_name: str
+
+
+def _info(si):
+    return Info(**si.as_dict())
+
+
+def opts(precision="fp64", tol=1e-10, max_iter=10000, inner_tol=0.0, max_outer=0, check_every=0):
+    return SolveOpts(PRECISIONS[precision], tol, max_iter, inner_tol, max_outer, check_every)
+
+
+class Context:
+    """One wf_ctx on a GPU.  Device memory comes from torch's caching allocator
+    and work goes on torch's current stream unless told otherwise."""
+
+    def __init__(self, device=0, stream=None, torch_allocator=True):
+        L = lib()
+        self._L = L
+        self.device = device
+        h = C.c_void_p()
+        self._cbs = (ALLOC_FN(), FREE_FN())
+        if torch_allocator:
+            import torch
+            torch.cuda.set_device(device)
+            self._cbs = _torch_allocator(device)
+            if stream is None:
+                stream = torch.cuda.current_stream(device).cuda_stream
+        self._check(L.wf_ctx_create(C.byref(h), device, stream, self._cbs[0], self._cbs[1], None), None)
+        self._h = h
+        self.n = None
+        self.box = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.wf_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, code, h="self", ok=(WF_OK,)):
+        if code in ok:
+            return code
+        if h == "self":
+            msg = self._L.wf_last_error(self._h)
+            msg = msg.decode() if msg else ""
+        else:
+            msg = self._L.wf_status_str(code).decode()
+        raise WienerError(code, msg)
+
+    # ---- inputs ---------------------------------------------------------
+    def set_grid(self, n, box):
+        self._check(self._L.wf_set_grid(self._h, int(n), float(box)))
+        self.n, self.box = int(n), float(box)
+
+    def set_mask(self, w):
+        w = _as_f64(w)
+        p, mem = _ptr(w)
+        self._check(self._L.wf_set_mask(self._h, p, mem))
+
+    def set_power(self, p_by_m2):
+        a = _as_f64(p_by_m2)
+        p, mem = _ptr(a)
+        self._check(self._L.wf_set_power(self._h, p, int(_numel(a)), mem))
+
+    def set_galaxies(self, xyz):
+        a = _as_f64(xyz)
+        p, mem = _ptr(a)
+        self._check(self._L.wf_set_galaxies(self._h, p, int(_numel(a) // 3), mem))
+
+    def deposit(self, scheme="cic", supersample=1):
+        self._check(self._L.wf_deposit(self._h, SCHEMES[scheme], int(supersample)))
+
+    def get_deposit(self, fine=True, n_obs=True, supersample=1):
+        n = self.n
+        nf = supersample * n
+        g = np.empty((nf, nf, nf), dtype=np.int64) if fine else None
+        o = np.empty((n, n, n), dtype=np.float64) if n_obs else None
+        nb = C.c_double()
+        self._check(self._L.wf_get_deposit(self._h, _ptr(g)[0], _ptr(o)[0], C.byref(nb), WF_HOST))
+        return g, o, nb.value
+
+    def set_rhs(self, b, nbar):
+        b = _as_f64(b)
+        p, mem = _ptr(b)
+        self._check(self._L.wf_set_rhs(self._h, p, float(nbar), mem))
+
+    def apply_operator(self, v, precision="fp64"):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        out = np.empty_like(v)
+        self._check(self._L.wf_apply_operator(self._h, PRECISIONS[precision], _ptr(v)[0],
+                                              _ptr(out)[0], WF_HOST))
+        return out
+
+    def forward_spectrum(self, v, precision="fp64"):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        n = self.n
+        out = np.empty((n, n, n // 2 + 1), dtype=np.complex128)
+        self._check(self._L.wf_forward_spectrum(self._h, PRECISIONS[precision], _ptr(v)[0],
+                                                out.ctypes.data, WF_HOST))
+        return out
+
+    # ---- solves ---------------------------------------------------------
+    def solve(self, out=None, allow=(WF_OK,), **kw):
+        o = opts(**kw)
+        n = self.n
+        if out is None:
+            out = np.empty((n, n, n), dtype=np.float64)
+        p, mem = _ptr(out)
+        si = SolveInfo()
+        code = self._L.wf_solve(self._h, C.byref(o), p, mem, C.byref(si))
+        self._check(code, ok=allow)
+        return out, _info(si)
+
+    def solve_begin(self, **kw):
+        o = opts(**kw)
+        self._check(self._L.wf_solve_begin(self._h, C.byref(o)))
+
+    def solve_step(self, iters):
+        d = C.c_int32()
+        self._check(self._L.wf_solve_step(self._h, int(iters), C.byref(d)))
+        return bool(d.value)
+
+    def snapshot(self):
+        nb = self._L.wf_snapshot_bytes(self._h)
+        buf = np.empty(nb, dtype=np.uint8)
+        self._check(self._L.wf_solve_snapshot(self._h, buf.ctypes.data, nb))
+        return buf
+
+    def resume(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self._L.wf_solve_resume(self._h, buf.ctypes.data, buf.size))
+
+    def solve_finish(self, allow=(WF_OK,)):
+        n = self.n
+        out = np.empty((n, n, n), dtype=np.float64)
+        si = SolveInfo()
+        self._check(self._L.wf_solve_finish(self._h, out.ctypes.data, WF_HOST, C.byref(si)), ok=allow)
+        return out, _info(si)
+
+    def solve_batch(self, catalogues, scheme="cic", supersample=2, outs=None,
+                    allow=(WF_OK,), **kw):
+        o = opts(**kw)
+        nr = len(catalogues)
+        cats = [_as_f64(c) for c in catalogues]
+        n = self.n
+        if outs is None:
+            outs = [np.empty((n, n, n), dtype=np.float64) for _ in range(nr)]
+        mem = _ptr(cats[0])[1] if nr else WF_HOST
+        xp = (C.c_void_p * nr)(*[_ptr(c)[0] for c in cats])
+        ng = (C.c_int64 * nr)(*[int(_numel(c) // 3) for c in cats])
+        op = (C.c_void_p * nr)(*[_ptr(x)[0] for x in outs])
+        infos = (SolveInfo * nr)()
+        code = self._L.wf_solve_batch(self._h, nr, xp, ng, SCHEMES[scheme], int(supersample),
+                                      C.byref(o), op, mem, infos)
+        self._check(code, ok=allow)
+        return outs, [_info(i) for i in infos]
+
+
+def footprint_bytes(n, supersample=2, precision="mixed", nrhs=1):
+    return int(lib().wf_footprint_bytes(n, supersample, PRECISIONS[precision], nrhs))
+
+
+def _as_f64(a):
+    if isinstance(a, np.ndarray):
+        return np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _numel(a):
+    if isinstance(a, np.ndarray):
+        return a.size
+    return a.numel()

@@ -1,0 +1,120 @@
+// Shared device helpers: complex arithmetic, deterministic block reductions,
+// the per-solve scalar state that lives on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wf {
+
+template <typename T> struct C2;
+template <> struct C2<float> { using type = float2; };
+template <> struct C2<double> { using type = double2; };
+template <typename T> using cplx = typename C2<T>::type;
+
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return {a.x + b.x, a.y + b.y}; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return {a.x - b.x, a.y - b.y}; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename V, typename T> __device__ __forceinline__ V cscale(V a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i (dir = -1) or +i (dir = +1)
+template <int DIR, typename V> __device__ __forceinline__ V mul_i(V a) {
+  if constexpr (DIR < 0) return {a.y, -a.x};
+  else return {-a.y, a.x};
+}
+
+// ---------------------------------------------------------------------------
+// Scalar state of one CG solve (one right-hand side), resident on the device.
+// Kernels read the scalars they need and skip all work once `done` is set, so
+// the host may enqueue iterations ahead of its convergence checks.
+// ---------------------------------------------------------------------------
+struct CgState {
+  double rho;        // r.r of the current residual
+  double bnorm;      // ||b|| of the system being iterated (inner: ||r_outer||-scaled rhs)
+  double tol;        // stop when sqrt(rho)/bnorm <= tol
+  double alpha, beta, pq;
+  double rel;        // last sqrt(rho)/bnorm
+  double nbar;       // mean density per cell of this right-hand side
+  double outer_rr;   // FP64 residual norm^2 of the refinement loop
+  double outer_bnorm;
+  double scale;      // 1/||r_outer|| used to normalise the inner rhs
+  int32_t iter;      // completed CG iterations (this inner solve)
+  int32_t max_iter;
+  int32_t done;      // 1: converged / max_iter / breakdown
+  int32_t status;    // 0 running, 1 converged, 2 max_iter, 3 breakdown
+  int32_t first;     // 1: next p-update is p = r
+  int32_t total_iter;// across inner solves
+  uint32_t ticket;   // last-block counter of the reductions
+  int32_t budget;    // refinement: inner iterations still allowed
+  double outer_tol;  // refinement: stop when sqrt(outer_rr)/outer_bnorm <= outer_tol
+  int32_t outer_status;  // refinement: 0 running, 1 converged, 2 budget spent, 3 breakdown, 4 stopped
+  int32_t outer_steps;
+};
+
+enum : int32_t { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN = 3, CG_STOPPED = 4 };
+
+// Coherent (device-scope) load of a value written by another workgroup of
+// the same kernel before its release fence.
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum over a 64-lane wavefront (fixed butterfly order: deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block sum, fixed order; every thread gets the result.  `sh` holds
+// blockDim/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// Writes this block's partial sum; returns true in the block that arrives
+// last (all partials visible to it).  The caller then calls
+// reduce_partials() and finishes the scalar update.  `flag` is LDS.
+__device__ __forceinline__ bool publish_partial(double part, double* partials,
+                                                uint32_t* ticket, uint32_t nblocks,
+                                                int* flag) {
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = part;
+    __threadfence();
+    uint32_t t = atomicAdd(ticket, 1u);
+    *flag = (t == nblocks - 1);
+  }
+  __syncthreads();
+  bool last = *flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Deterministic sum of partials[0..n): each thread sums a fixed strided
+// subset, then a fixed tree.
+__device__ __forceinline__ double reduce_partials(const double* partials, uint32_t n,
+                                                  double* sh) {
+  double s = 0.0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s += load_agent(partials + i);
+  return block_sum(s, sh);
+}
+
+__device__ __forceinline__ void reset_ticket(uint32_t* ticket) {
+  __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace wf

@@ -1,0 +1,398 @@
+// Host-side building blocks: device memory, twiddles, the operator pipeline
+// and the gridding pipeline.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace wf {
+
+void* Allocator::get(size_t bytes) const {
+  if (bytes == 0) bytes = 256;
+  if (alloc) return alloc(bytes, user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void Allocator::put(void* p) const {
+  if (!p) return;
+  if (free_fn) free_fn(p, user);
+  else (void)hipFree(p);
+}
+
+void DevBuf::release() {
+  if (p && a) a->put(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+Status DevBuf::ensure(const Allocator& al, size_t b) {
+  if (p && bytes >= b && a == &al) return {};
+  release();
+  a = &al;
+  p = al.get(b);
+  if (!p) return fail(WF_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+  bytes = b;
+  return {};
+}
+
+void Grid::set(int n_, double box_) {
+  n = n_;
+  box = box_;
+  m = (int64_t)n * n * n;
+  nrows = (int64_t)n * n;
+  spec_main = (int64_t)n * n * (n / 2);
+  spec_total = spec_main + (int64_t)n * n;
+  lamlen = 3 * (int64_t)(n / 2) * (n / 2) + 1;
+}
+
+SolveWork::~SolveWork() {
+  if (st_host) (void)hipHostFree(st_host);
+}
+
+Status SolveWork::ensure(const Allocator& al, const Grid& g, int nr, bool fp64_cg, bool mixed) {
+  nrhs = nr;
+  const size_t m = (size_t)g.m * nr;
+  const size_t sp = (size_t)g.spec_total * nr;
+  WF_TRY(b64.ensure(al, m * 8));
+  WF_TRY(x64.ensure(al, m * 8));
+  WF_TRY(r64.ensure(al, m * 8));
+  WF_TRY(spec64.ensure(al, sp * 16));
+  if (fp64_cg) {
+    WF_TRY(p64.ensure(al, m * 8));
+    WF_TRY(q64.ensure(al, m * 8));
+  }
+  if (mixed) {
+    WF_TRY(x32.ensure(al, m * 4));
+    WF_TRY(r32.ensure(al, m * 4));
+    WF_TRY(p32.ensure(al, m * 4));
+    WF_TRY(q32.ensure(al, m * 4));
+    WF_TRY(spec32.ensure(al, sp * 8));
+  }
+  // partials: enough for the largest grid of any reduction kernel per RHS
+  const int64_t zblocks = g.nrows / 2;  // upper bound of z-pass blocks (NB >= 1)
+  const int64_t per = std::max<int64_t>(zblocks, 2048);
+  WF_TRY(partials.ensure(al, (size_t)per * nr * 8));
+  WF_TRY(state.ensure(al, sizeof(CgState) * nr));
+  if (st_cap < nr) {
+    if (st_host) (void)hipHostFree(st_host);
+    st_host = nullptr;
+    WF_HIP(hipHostMalloc((void**)&st_host, sizeof(CgState) * nr, hipHostMallocDefault));
+    st_cap = nr;
+  }
+  return {};
+}
+
+Status SolveWork::pull_state(hipStream_t s) {
+  WF_HIP(hipMemcpyAsync(st_host, state.p, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, s));
+  WF_HIP(hipStreamSynchronize(s));
+  return {};
+}
+
+Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32) {
+  std::vector<double> t(2 * (size_t)n);
+  std::vector<float> f(2 * (size_t)n);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int m = 0; m < n; ++m) {
+    // exp(-2 pi i m / n), reduced to the first octant for accuracy
+    long double ang = (long double)two_pi * (long double)m / (long double)n;
+    double c = (double)cosl(ang), s = -(double)sinl(ang);
+    if (4 * m == n) { c = 0.0; s = -1.0; }
+    if (2 * m == n) { c = -1.0; s = 0.0; }
+    if (4 * m == 3 * n) { c = 0.0; s = 1.0; }
+    if (m == 0) { c = 1.0; s = 0.0; }
+    t[2 * m] = c;
+    t[2 * m + 1] = s;
+    f[2 * m] = (float)c;
+    f[2 * m + 1] = (float)s;
+  }
+  WF_TRY(tw64.ensure(al, t.size() * 8));
+  WF_HIP(hipMemcpy(tw64.p, t.data(), t.size() * 8, hipMemcpyHostToDevice));
+  if (tw32) {
+    WF_TRY(tw32->ensure(al, f.size() * 4));
+    WF_HIP(hipMemcpy(tw32->p, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  }
+  return {};
+}
+
+Status upload(void* dst, const void* src, size_t bytes, wf_mem mem, hipStream_t s) {
+  if (bytes == 0) return {};
+  WF_HIP(hipMemcpyAsync(dst, src, bytes,
+                        mem == WF_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+  if (mem == WF_HOST) WF_HIP(hipStreamSynchronize(s));
+  return {};
+}
+
+Status download(void* dst, const void* src, size_t bytes, wf_mem mem, hipStream_t s) {
+  if (bytes == 0) return {};
+  WF_HIP(hipMemcpyAsync(dst, src, bytes,
+                        mem == WF_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  if (mem == WF_HOST) WF_HIP(hipStreamSynchronize(s));
+  return {};
+}
+
+// ---------------------------------------------------------------------------
+// segment descriptors of the strided passes
+// ---------------------------------------------------------------------------
+template <typename T> static Seg<T> seg_y_main(cplx<T>* spec, const Grid& g, int tb) {
+  Seg<T> s{};
+  const int64_t h = g.n / 2;
+  s.in = spec;
+  s.out = spec;
+  s.in_outer = s.out_outer = g.n * h;
+  s.in_axis = s.out_axis = h;
+  s.in_batch = s.out_batch = 1;
+  s.in_rhs = s.out_rhs = g.spec_total;
+  s.n_outer = g.n;
+  s.n_btiles = (int)(h / tb);
+  s.n_out = g.n;
+  return s;
+}
+template <typename T> static Seg<T> seg_y_nyq(cplx<T>* nyq, const Grid& g, int tb) {
+  Seg<T> s{};
+  s.in = nyq;
+  s.out = nyq;
+  s.in_axis = s.out_axis = 1;
+  s.in_batch = s.out_batch = g.n;
+  s.in_rhs = s.out_rhs = g.spec_total;
+  s.n_outer = 1;
+  s.n_btiles = g.n / tb;
+  s.axis_contig = 1;
+  s.n_out = g.n;
+  return s;
+}
+template <typename T> static Seg<T> seg_x_main(cplx<T>* spec, const Grid& g, int tb) {
+  Seg<T> s{};
+  const int64_t h = g.n / 2;
+  s.in = spec;
+  s.out = spec;
+  s.in_outer = s.out_outer = h;
+  s.in_axis = s.out_axis = g.n * h;
+  s.in_batch = s.out_batch = 1;
+  s.in_rhs = s.out_rhs = g.spec_total;
+  s.n_outer = g.n;
+  s.n_btiles = (int)(h / tb);
+  s.n_out = g.n;
+  s.lam_outer_signed = 1;
+  return s;
+}
+template <typename T> static Seg<T> seg_x_nyq(cplx<T>* nyq, const Grid& g, int tb) {
+  Seg<T> s{};
+  s.in = nyq;
+  s.out = nyq;
+  s.in_axis = s.out_axis = g.n;
+  s.in_batch = s.out_batch = 1;
+  s.in_rhs = s.out_rhs = g.spec_total;
+  s.n_outer = 1;
+  s.n_btiles = g.n / tb;
+  s.n_out = g.n;
+  s.lam_batch_signed = 1;
+  s.lam_const = (g.n / 2) * (g.n / 2);
+  return s;
+}
+
+template <typename T> static const cplx<T>* tw_of(const OperatorData& od) {
+  if constexpr (sizeof(T) == 8) return od.tw64.as<cplx<T>>();
+  else return od.tw32.as<cplx<T>>();
+}
+template <typename T> static const T* lam_of(const OperatorData& od) {
+  if constexpr (sizeof(T) == 8) return od.lam64.as<T>();
+  else return od.lam32.as<T>();
+}
+template <typename T> static const T* w_of(const OperatorData& od) {
+  if constexpr (sizeof(T) == 8) return od.w64.as<T>();
+  else return od.w32.as<T>();
+}
+
+template <typename T>
+static StrArgs<T> str_args(const OperatorData& od, cplx<T>* spec, bool xpass, const CgState* st) {
+  const Grid& g = od.g;
+  const int tb = strided_tb(g.n, sizeof(T) == 8);
+  cplx<T>* nyq = spec + g.spec_main;
+  StrArgs<T> a{};
+  a.s0 = xpass ? seg_x_main<T>(spec, g, tb) : seg_y_main<T>(spec, g, tb);
+  a.s1 = xpass ? seg_x_nyq<T>(nyq, g, tb) : seg_y_nyq<T>(nyq, g, tb);
+  a.nblk0 = a.s0.n_outer * a.s0.n_btiles;
+  a.nblk1 = a.s1.n_outer * a.s1.n_btiles;
+  a.lam = lam_of<T>(od);
+  a.tw = tw_of<T>(od);
+  a.st = st;
+  return a;
+}
+
+template <typename T>
+Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T* p,
+                       cplx<T>* spec, int zout_mode, T* out, const T* aux, const double* bvec,
+                       CgState* st, double* partials, int nrhs, bool check_done, hipStream_t s) {
+  const Grid& g = od.g;
+  ZfwdArgs<T> zf{};
+  zf.in = in_or_r;
+  zf.p = p;
+  zf.out_main = spec;
+  zf.out_nyq = spec + g.spec_main;
+  zf.nkz_out = g.n / 2;
+  zf.rhs_in = g.m;
+  zf.rhs_main = g.spec_total;
+  zf.rhs_nyq = g.spec_total;
+  zf.tw = tw_of<T>(od);
+  zf.st = (zin_mode == ZIN_CGP) ? st : nullptr;
+  WF_HIP(launch_zfwd<T>(g.n, zin_mode, zf, g.nrows, nrhs, s));
+
+  const CgState* sc = check_done ? st : nullptr;
+  WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, false, sc), nrhs, s));
+  WF_HIP(launch_strided<T>(g.n, SM_FWD_LAM_INV, str_args<T>(od, spec, true, sc), nrhs, s));
+  WF_HIP(launch_strided<T>(g.n, SM_INV, str_args<T>(od, spec, false, sc), nrhs, s));
+
+  ZinvArgs<T> zi{};
+  zi.in_main = spec;
+  zi.in_nyq = spec + g.spec_main;
+  zi.rhs_main = g.spec_total;
+  zi.rhs_nyq = g.spec_total;
+  zi.out = out;
+  zi.rhs_out = g.m;
+  zi.aux = aux;
+  zi.rhs_aux = g.m;
+  zi.w = w_of<T>(od);
+  zi.bvec = bvec;
+  zi.rhs_b = g.m;
+  zi.scale = 1.0;
+  zi.partials = partials;
+  zi.tw = tw_of<T>(od);
+  zi.st = st;
+  WF_HIP(launch_zinv<T>(g.n, zout_mode, zi, g.nrows, nrhs, s));
+  return {};
+}
+
+template Status operator_passes<float>(const OperatorData&, int, const float*, float*, cplx<float>*,
+                                       int, float*, const float*, const double*, CgState*, double*,
+                                       int, bool, hipStream_t);
+template Status operator_passes<double>(const OperatorData&, int, const double*, double*,
+                                        cplx<double>*, int, double*, const double*, const double*,
+                                        CgState*, double*, int, bool, hipStream_t);
+
+template <typename T>
+Status forward_passes(const OperatorData& od, const T* in, cplx<T>* spec, hipStream_t s) {
+  const Grid& g = od.g;
+  ZfwdArgs<T> zf{};
+  zf.in = in;
+  zf.out_main = spec;
+  zf.out_nyq = spec + g.spec_main;
+  zf.nkz_out = g.n / 2;
+  zf.rhs_in = g.m;
+  zf.rhs_main = g.spec_total;
+  zf.rhs_nyq = g.spec_total;
+  zf.tw = tw_of<T>(od);
+  WF_HIP(launch_zfwd<T>(g.n, ZIN_REAL, zf, g.nrows, 1, s));
+  WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, false, nullptr), 1, s));
+  WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, true, nullptr), 1, s));
+  return {};
+}
+template Status forward_passes<float>(const OperatorData&, const float*, cplx<float>*, hipStream_t);
+template Status forward_passes<double>(const OperatorData&, const double*, cplx<double>*,
+                                       hipStream_t);
+
+// ---------------------------------------------------------------------------
+// gridding: deposit, then (s = 2) low-pass and resample (Sec. 3.1.2)
+// ---------------------------------------------------------------------------
+Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
+                   const double* xyz, int64_t ngal, int scheme, int ss, double* nobs,
+                   hipStream_t s) {
+  const Grid& g = od.g;
+  const int n = g.n, nf = ss * n;
+  const int64_t mf = (int64_t)nf * nf * nf;
+  WF_TRY(dw.grid.ensure(al, (size_t)mf * 8));
+  long long* grid = dw.grid.as<long long>();
+  WF_HIP(launch_fill_i64(grid, mf, s));
+  const double c = (double)nf / g.box;
+  WF_HIP(launch_deposit(scheme, xyz, ngal, c, nf, grid, s));
+  const double unit = scheme == WF_NGP ? 1.0 : std::ldexp(1.0, -39);
+  if (ss == 1) {
+    WF_HIP(launch_i64_to_f64(nobs, grid, unit, g.m, s));
+    return {};
+  }
+  // fine forward transform, keeping kz < n/2
+  const int h = n / 2;
+  if (dw.tw_fine.bytes < (size_t)nf * 16) WF_TRY(make_twiddles(al, nf, dw.tw_fine, nullptr));
+  const int64_t fine_spec = (int64_t)nf * nf * h;
+  WF_TRY(dw.fine_spec.ensure(al, (size_t)fine_spec * 16));
+  auto* fs = dw.fine_spec.as<double2>();
+  const auto* twf = dw.tw_fine.as<double2>();
+  ZfwdArgs<double> zf{};
+  zf.gin = grid;
+  zf.unit = unit;
+  zf.out_main = fs;
+  zf.out_nyq = nullptr;
+  zf.nkz_out = h;
+  zf.tw = twf;
+  WF_HIP(launch_zfwd<double>(nf, ZIN_I64, zf, (int64_t)nf * nf, 1, s));
+
+  // y: fine [nf x][nf y][h] -> [nf x][n y][h], keeping |m_y| < n/2
+  const int tbf = strided_tb(nf, true);
+  const int64_t ysz = (int64_t)nf * n * h;
+  WF_TRY(dw.spec_y.ensure(al, (size_t)ysz * 16));
+  auto* sy = dw.spec_y.as<double2>();
+  {
+    StrArgs<double> a{};
+    Seg<double>& q = a.s0;
+    q.in = fs;
+    q.out = sy;
+    q.in_outer = (int64_t)nf * h;
+    q.in_axis = h;
+    q.in_batch = 1;
+    q.out_outer = (int64_t)n * h;
+    q.out_axis = h;
+    q.out_batch = 1;
+    q.n_outer = nf;
+    q.n_btiles = h / tbf;
+    q.n_out = n;
+    a.nblk0 = q.n_outer * q.n_btiles;
+    a.nblk1 = 0;
+    a.tw = twf;
+    WF_HIP(launch_strided<double>(nf, SM_FWD_CROP, a, 1, s));
+  }
+  // x: [nf x][n y][h] -> coarse main [n x][n y][h], keeping |m_x| < n/2
+  WF_TRY(dw.spec_c.ensure(al, (size_t)g.spec_total * 16));
+  auto* sc = dw.spec_c.as<double2>();
+  {
+    StrArgs<double> a{};
+    Seg<double>& q = a.s0;
+    q.in = sy;
+    q.out = sc;
+    q.in_outer = h;
+    q.in_axis = (int64_t)n * h;
+    q.in_batch = 1;
+    q.out_outer = h;
+    q.out_axis = (int64_t)n * h;
+    q.out_batch = 1;
+    q.n_outer = n;
+    q.n_btiles = h / tbf;
+    q.n_out = n;
+    a.nblk0 = q.n_outer * q.n_btiles;
+    a.nblk1 = 0;
+    a.tw = twf;
+    WF_HIP(launch_strided<double>(nf, SM_FWD_CROP, a, 1, s));
+  }
+  // the target Nyquist planes are dropped
+  WF_HIP(launch_fill_c64(sc + g.spec_main, (int64_t)n * n, s));
+  // coarse inverse: x, y, then z to real with 1/n^3
+  WF_HIP(launch_strided<double>(n, SM_INV, str_args<double>(od, sc, true, nullptr), 1, s));
+  WF_HIP(launch_strided<double>(n, SM_INV, str_args<double>(od, sc, false, nullptr), 1, s));
+  ZinvArgs<double> zi{};
+  zi.in_main = sc;
+  zi.in_nyq = sc + g.spec_main;
+  zi.out = nobs;
+  zi.scale = 1.0 / (double)g.m;
+  zi.tw = od.tw64.as<double2>();
+  WF_HIP(launch_zinv<double>(n, ZOUT_REAL, zi, g.nrows, 1, s));
+  return {};
+}
+
+double model_bytes_iteration(bool fp64) { return fp64 ? 160.0 : 80.0; }
+double model_bytes_residual() { return 104.0; }
+
+}  // namespace wf

@@ -1,0 +1,125 @@
+// Host-side internals shared by the context API, the batch driver and the
+// server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/wiener.h"
+#include "launch.h"
+
+namespace wf {
+
+struct Status {
+  wf_status code = WF_OK;
+  std::string msg;
+  bool ok() const { return code == WF_OK; }
+};
+
+inline Status fail(wf_status c, std::string m) { return Status{c, std::move(m)}; }
+inline Status hip_fail(hipError_t e, const char* what) {
+  return Status{WF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+#define WF_HIP(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+#define WF_TRY(expr)            \
+  do {                          \
+    Status s_ = (expr);         \
+    if (!s_.ok()) return s_;    \
+  } while (0)
+
+// Device allocator: caller callbacks or hipMalloc.
+struct Allocator {
+  wf_alloc_fn alloc = nullptr;
+  wf_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  int device = 0;
+  void* get(size_t bytes) const;
+  void put(void* p) const;
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  const Allocator* a = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release();
+  Status ensure(const Allocator& al, size_t b);  // keeps contents only if big enough already
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Per-grid FFT resources for one precision.
+template <typename T> struct Spectral {
+  DevBuf tw;     // tw[m] = exp(-2 pi i m / n)
+};
+
+// Geometry of one n^3 grid and its half spectrum layout.
+struct Grid {
+  int n = 0;
+  double box = 0.0;
+  int64_t m = 0;        // n^3
+  int64_t nrows = 0;    // n^2
+  int64_t spec_main = 0;  // n * n * n/2 complex
+  int64_t spec_total = 0; // + n * n (Nyquist plane)
+  int64_t lamlen = 0;   // 3 (n/2)^2 + 1
+  void set(int n_, double box_);
+};
+
+// The operator's constant data on the device (shared by every RHS of a grid).
+struct OperatorData {
+  Grid g;
+  DevBuf w64, w32, lam64, lam32, tw64, tw32;
+};
+
+// Workspace of solves on a grid for `nrhs` right-hand sides.
+struct SolveWork {
+  int nrhs = 0;
+  DevBuf b64, x64, r64, p64, q64, spec64;
+  DevBuf x32, r32, p32, q32, spec32;
+  DevBuf state, partials;
+  CgState* st_host = nullptr;   // pinned mirror of the state array
+  int st_cap = 0;
+  ~SolveWork();
+  // b, x, r and the FP64 spectrum always; p, q (FP64 CG); the FP32 set (mixed)
+  Status ensure(const Allocator& al, const Grid& g, int nrhs, bool fp64_cg, bool mixed);
+  Status pull_state(hipStream_t s);
+};
+
+Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32);
+Status upload(void* dst, const void* src, size_t bytes, wf_mem mem, hipStream_t s);
+Status download(void* dst, const void* src, size_t bytes, wf_mem mem, hipStream_t s);
+
+// Operator pipeline (five sweeps) on `nrhs` vectors laid out with stride g.m.
+template <typename T>
+Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T* p,
+                       cplx<T>* spec, int zout_mode, T* out, const T* aux,
+                       const double* bvec, CgState* st, double* partials, int nrhs,
+                       bool check_done, hipStream_t s);
+
+// Forward transform only (test hook): z, y, x forward passes.
+template <typename T>
+Status forward_passes(const OperatorData& od, const T* in, cplx<T>* spec, hipStream_t s);
+
+// Gridding of one catalogue into n_obs (n^3 doubles) -- Sec. 3.1.2.
+struct DepositWork {
+  DevBuf grid, fine_spec, spec_y, spec_c, tw_fine, flag;
+};
+Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
+                   const double* xyz_dev, int64_t ngal, int scheme, int supersample,
+                   double* nobs_dev, hipStream_t s);
+
+// Algorithmic HBM bytes of one CG iteration (model of the five sweeps plus
+// the vector update) and of one FP64 residual recomputation, per cell.
+double model_bytes_iteration(bool fp64);
+double model_bytes_residual();
+
+}  // namespace wf

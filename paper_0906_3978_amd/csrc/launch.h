@@ -1,0 +1,121 @@
+// Kernel argument blocks and launchers (host side of kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace wf {
+
+// ---- z-axis passes (contiguous rows, real <-> half spectrum) --------------
+enum ZinMode : int { ZIN_REAL = 0, ZIN_CGP = 1, ZIN_I64 = 2 };
+enum ZoutMode : int { ZOUT_REAL = 0, ZOUT_CGQ = 1, ZOUT_RES = 2, ZOUT_APPLY = 3 };
+
+template <typename T> struct ZfwdArgs {
+  const T* in;              // ZIN_REAL: rows; ZIN_CGP: r
+  T* p;                     // ZIN_CGP: search direction, updated in place
+  const long long* gin;     // ZIN_I64: integer rows
+  double unit;              // ZIN_I64: value of one integer unit
+  cplx<T>* out_main;        // [row][nkz_out]
+  cplx<T>* out_nyq;         // [row] (kz = N/2) or null
+  int32_t nkz_out;
+  int64_t rhs_in, rhs_main, rhs_nyq;  // per-RHS strides in elements
+  const cplx<T>* tw;
+  CgState* st;              // may be null
+};
+
+template <typename T> struct ZinvArgs {
+  const cplx<T>* in_main;   // [row][N/2]
+  const cplx<T>* in_nyq;    // [row]
+  int64_t rhs_main, rhs_nyq;
+  T* out;                   // real rows
+  int64_t rhs_out;
+  const T* aux;             // CGQ: p; RES: x; APPLY: v
+  int64_t rhs_aux;
+  const T* w;               // mask (shared by all RHS)
+  const double* bvec;       // RES: b
+  int64_t rhs_b;
+  double scale;             // REAL: output scale
+  double* partials;         // per RHS: gridDim.x doubles
+  const cplx<T>* tw;
+  CgState* st;
+};
+
+// ---- strided passes (y or x axis), tiles of TB neighbouring pencils -------
+enum StrMode : int { SM_FWD = 0, SM_INV = 1, SM_FWD_LAM_INV = 2, SM_FWD_CROP = 3 };
+
+template <typename T> struct Seg {
+  const cplx<T>* in;
+  cplx<T>* out;
+  int64_t in_outer, in_axis, in_batch, in_rhs;
+  int64_t out_outer, out_axis, out_batch, out_rhs;
+  int32_t n_outer, n_btiles, axis_contig, n_out;
+  int32_t lam_outer_signed, lam_batch_signed, lam_const, pad;
+};
+
+template <typename T> struct StrArgs {
+  Seg<T> s0, s1;
+  int32_t nblk0, nblk1;
+  const T* lam;
+  const cplx<T>* tw;
+  const CgState* st;
+};
+
+int strided_tb(int n, bool fp64);   // batch width of a strided tile
+int zpass_nb(int n, bool fp64);     // pencils (row pairs) per z-pass block
+bool fft_length_supported(int n, bool fp64);
+
+template <typename T> hipError_t launch_zfwd(int n, int mode, const ZfwdArgs<T>& a,
+                                             int64_t nrows, int nrhs, hipStream_t s);
+template <typename T> hipError_t launch_zinv(int n, int mode, const ZinvArgs<T>& a,
+                                             int64_t nrows, int nrhs, hipStream_t s);
+template <typename T> hipError_t launch_strided(int n, int mode, const StrArgs<T>& a,
+                                                int nrhs, hipStream_t s);
+
+// ---- vector kernels --------------------------------------------------------
+constexpr int VEC_THREADS = 256;
+int vec_blocks(int64_t m);
+
+// x = 0; r = (T)(src * (scaled ? st->scale : 1)); rho = r.r; bnorm; starts a CG solve
+template <typename T> hipError_t launch_cg_init(T* x, T* r, const double* src, int64_t m,
+                                                int64_t rhs_stride, int scaled, double* partials,
+                                                CgState* st, int nrhs, hipStream_t s);
+// x += alpha p; r -= alpha q; rho' = r.r; convergence test; beta
+template <typename T> hipError_t launch_cg_update(T* x, T* r, const T* p, const T* q, int64_t m,
+                                                  int64_t rhs_stride, double* partials,
+                                                  CgState* st, int nrhs, hipStream_t s);
+// refinement: x64 += sqrt(outer_rr) * e32
+hipError_t launch_refine_add(double* x, const float* e, int64_t m, int64_t rhs_stride,
+                             const CgState* st, int nrhs, hipStream_t s);
+// r = b, x = 0, outer_rr = b.b, outer_bnorm
+hipError_t launch_outer_init(double* x, double* r, const double* b, int64_t m, int64_t rhs_stride,
+                             double* partials, CgState* st, int nrhs, hipStream_t s);
+// refinement: start the next inner solve (per-RHS outer test, budget, scale)
+hipError_t launch_inner_setup(CgState* st, double tol, int nrhs, hipStream_t s);
+// refinement: charge the inner iterations to the budget, note breakdowns
+hipError_t launch_inner_finish(CgState* st, int nrhs, hipStream_t s);
+
+hipError_t launch_fill_i64(long long* p, int64_t n, hipStream_t s);
+hipError_t launch_fill_c64(double2* p, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s);
+hipError_t launch_f64_to_f32(float* out, const double* in, int64_t n, hipStream_t s);
+hipError_t launch_f32_to_f64(double* out, const float* in, int64_t n, hipStream_t s);
+hipError_t launch_i64_to_f64(double* out, const long long* in, double unit, int64_t n,
+                             hipStream_t s);
+
+// ---- deposit / inputs ------------------------------------------------------
+hipError_t launch_check_xyz(const double* xyz, int64_t ngal, double box, int* flag, hipStream_t s);
+hipError_t launch_deposit(int scheme, const double* xyz, int64_t ngal, double c, int nd,
+                          long long* grid, hipStream_t s);
+// validates w (finite, 0 <= w <= 1), copies to w64/w32 and writes sum(w) to *sumw
+hipError_t launch_mask(const double* w, double* w64, float* w32, int64_t m, int* flag,
+                       double* partials, uint32_t* ticket, double* sumw, hipStream_t s);
+// lam[j] = (dv / p[j]) * inv_m for j >= 1, lam[0] = 0; flags non-finite or <= 0
+hipError_t launch_lambda(const double* p, int64_t len, double dv, double inv_m, double* lam64,
+                         float* lam32, int* flag, hipStream_t s);
+// nbar = ngal / sumw; b = w > 0 ? nobs - nbar w : 0
+hipError_t launch_data_vector(const double* nobs, const double* w, const double* sumw, double ngal,
+                              double* nbar_out, double* b, int64_t m, hipStream_t s);
+
+}  // namespace wf

@@ -1,0 +1,49 @@
+// Solve drivers: FP64 conjugate gradients, mixed-precision iterative
+// refinement, the multi-RHS batch, checkpoint/resume.
+#pragma once
+
+#include "internal.h"
+
+namespace wf {
+
+Status validate_opts(const wf_solve_opts& o);
+
+struct SolveRequest {
+  const OperatorData* od = nullptr;
+  const Allocator* al = nullptr;
+  SolveWork* work = nullptr;   // b64 holds nrhs right-hand sides
+  int nrhs = 1;
+  const double* nbar = nullptr;  // nrhs values
+  wf_solve_opts opts{};
+  hipStream_t stream = nullptr;
+};
+
+// Solves every RHS from x = 0; x64 of the work holds the solutions.
+// Returns the worst status; infos[i] per RHS.
+Status run_solve(const SolveRequest& rq, wf_solve_info* infos);
+
+// Stepwise FP64 solve of one RHS (checkpoint / resume).
+Status fp64_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, double nbar,
+                  const wf_solve_opts& o, hipStream_t s);
+Status fp64_iterations(const OperatorData& od, SolveWork& sw, int iters, hipStream_t s);
+Status fp64_finish(const OperatorData& od, SolveWork& sw, hipStream_t s, wf_solve_info* info);
+size_t snapshot_bytes(const Grid& g);
+Status snapshot_save(const Grid& g, SolveWork& sw, void* buf, hipStream_t s);
+Status snapshot_load(const OperatorData& od, const Allocator& al, SolveWork& sw, const void* buf,
+                     hipStream_t s);
+
+struct BatchInputs {
+  int nrhs = 0;
+  const double* const* xyz = nullptr;
+  const int64_t* n_gal = nullptr;
+  int scheme = 0;
+  int ss = 1;
+  wf_mem mem = WF_HOST;
+};
+Status run_batch(const OperatorData& od, const Allocator& al, DepositWork& dw,
+                 const BatchInputs& bi, const wf_solve_opts& o, double* const* s_out,
+                 wf_solve_info* infos, double sumw, hipStream_t s);
+
+size_t footprint_bytes(int n, int ss, wf_precision prec, int nrhs);
+
+}  // namespace wf

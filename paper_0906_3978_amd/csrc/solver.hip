@@ -1,0 +1,404 @@
+// Conjugate-gradient drivers for the Wiener system A s = b (eq:WF).
+//
+// FP64: plain CG from s = 0 (Hestenes-Stiefel), stopped on the recursive
+// relative residual.  MIXED: FP64 iterative refinement around FP32 CG --
+// r = b - A64 x (FP64 FFTs and diagonals), inner FP32 CG on r / ||r|| with
+// FP64 dot products down to inner_tol, x += ||r|| e -- stopped on the FP64
+// residual.  Both run several right-hand sides at once when asked: every
+// kernel launch covers all of them, each with its own scalars and stop flag.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "solver.h"
+
+namespace wf {
+
+Status validate_opts(const wf_solve_opts& o) {
+  if (o.precision != WF_FP64 && o.precision != WF_MIXED) return fail(WF_EINVAL, "unknown precision");
+  if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(WF_EINVAL, "tol must be finite and >= 0");
+  if (o.max_iter < 0) return fail(WF_EINVAL, "max_iter must be >= 0");
+  if (!(o.inner_tol >= 0.0) || o.inner_tol >= 1.0) return fail(WF_EINVAL, "inner_tol must be in [0, 1)");
+  if (o.max_outer < 0 || o.check_every < 0) return fail(WF_EINVAL, "max_outer and check_every must be >= 0");
+  return {};
+}
+
+namespace {
+
+template <typename T> struct Vecs {
+  T *x, *r, *p, *q;
+  cplx<T>* spec;
+};
+Vecs<double> v64(SolveWork& sw) {
+  return {sw.x64.as<double>(), sw.r64.as<double>(), sw.p64.as<double>(), sw.q64.as<double>(),
+          sw.spec64.as<double2>()};
+}
+Vecs<float> v32(SolveWork& sw) {
+  return {sw.x32.as<float>(), sw.r32.as<float>(), sw.p32.as<float>(), sw.q32.as<float>(),
+          sw.spec32.as<float2>()};
+}
+
+template <typename T>
+Status cg_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hipStream_t s) {
+  CgState* st = sw.state.as<CgState>();
+  double* parts = sw.partials.as<double>();
+  WF_TRY(operator_passes<T>(od, ZIN_CGP, v.r, v.p, v.spec, ZOUT_CGQ, v.q, v.p, nullptr, st, parts,
+                            nr, true, s));
+  WF_HIP(launch_cg_update<T>(v.x, v.r, v.p, v.q, od.g.m, od.g.m, parts, st, nr, s));
+  return {};
+}
+
+// Runs CG iterations in chunks of `check` until every RHS is done.
+template <typename T>
+Status iterate_until_done(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, int check,
+                          hipStream_t s) {
+  for (;;) {
+    WF_TRY(sw.pull_state(s));
+    bool all = true;
+    for (int i = 0; i < nr; ++i) all = all && sw.st_host[i].done;
+    if (all) return {};
+    for (int k = 0; k < check; ++k) WF_TRY(cg_iteration<T>(od, sw, v, nr, s));
+  }
+}
+
+wf_status map_cg_status(int32_t st) {
+  switch (st) {
+    case CG_CONVERGED: return WF_OK;
+    case CG_MAXITER: return WF_ENOTCONV;
+    case CG_BREAKDOWN: return WF_EBREAKDOWN;
+    case CG_STOPPED: return WF_ENOTCONV;
+    default: return WF_ENOTCONV;
+  }
+}
+
+int severity(wf_status s) {
+  switch (s) {
+    case WF_OK: return 0;
+    case WF_ENOTCONV: return 1;
+    case WF_EBREAKDOWN: return 2;
+    default: return 3;
+  }
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer() {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  void start(hipStream_t s) { (void)hipEventRecord(a, s); }
+  double stop(hipStream_t s) {
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+  }
+};
+
+Status push_states(SolveWork& sw, const std::vector<CgState>& st, hipStream_t s) {
+  std::memcpy(sw.st_host, st.data(), sizeof(CgState) * st.size());
+  WF_HIP(hipMemcpyAsync(sw.state.p, sw.st_host, sizeof(CgState) * st.size(), hipMemcpyHostToDevice, s));
+  WF_HIP(hipStreamSynchronize(s));
+  return {};
+}
+
+// r_true = b - A64 x into `out`; outer_rr = ||r_true||^2 per RHS.
+Status true_residual(const OperatorData& od, SolveWork& sw, double* out, int nr, hipStream_t s) {
+  return operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr,
+                                 sw.spec64.as<double2>(), ZOUT_RES, out, sw.x64.as<double>(),
+                                 sw.b64.as<double>(), sw.state.as<CgState>(),
+                                 sw.partials.as<double>(), nr, false, s);
+}
+
+}  // namespace
+
+Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
+  const OperatorData& od = *rq.od;
+  const Grid& g = od.g;
+  SolveWork& sw = *rq.work;
+  const int nr = rq.nrhs;
+  const hipStream_t s = rq.stream;
+  const wf_solve_opts& o = rq.opts;
+  const bool mixed = o.precision == WF_MIXED;
+  const int check = o.check_every > 0 ? o.check_every : 16;
+  WF_TRY(sw.ensure(*rq.al, g, nr, !mixed, mixed));
+  std::vector<CgState> st(nr);
+  for (int i = 0; i < nr; ++i) {
+    st[i] = CgState{};
+    st[i].nbar = rq.nbar[i];
+  }
+  Timer tm;
+  const double M = (double)g.m;
+  Status worst{};
+  if (!mixed) {
+    for (auto& e : st) {
+      e.tol = o.tol;
+      e.max_iter = o.max_iter;
+    }
+    WF_TRY(push_states(sw, st, s));
+    tm.start(s);
+    Vecs<double> v = v64(sw);
+    WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), g.m, g.m, 0,
+                                  sw.partials.as<double>(), sw.state.as<CgState>(), nr, s));
+    WF_TRY(iterate_until_done<double>(od, sw, v, nr, check, s));
+    WF_TRY(true_residual(od, sw, v.q, nr, s));
+    const double ms = tm.stop(s);
+    WF_TRY(sw.pull_state(s));
+    for (int i = 0; i < nr; ++i) {
+      const CgState& c = sw.st_host[i];
+      wf_solve_info& in = infos[i];
+      in = wf_solve_info{};
+      in.iters_total = c.iter;
+      in.outer_steps = 0;
+      in.rel_res_recursive = c.bnorm > 0 ? c.rel : 0.0;
+      in.rel_res_true = c.bnorm > 0 ? std::sqrt(c.outer_rr) / c.bnorm : 0.0;
+      in.time_ms = ms;
+      in.model_bytes = (c.iter * model_bytes_iteration(true) + model_bytes_residual()) * M;
+      in.nbar = c.nbar;
+      in.status = map_cg_status(c.status);
+      if (severity((wf_status)in.status) > severity(worst.code))
+        worst = fail((wf_status)in.status, std::string("rhs ") + std::to_string(i) + ": " +
+                                               wf_status_str((wf_status)in.status));
+    }
+    return worst;
+  }
+
+  // ---- mixed precision: FP64 refinement around FP32 CG -------------------
+  const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+  const int max_outer = o.max_outer > 0 ? o.max_outer : 16;
+  for (auto& e : st) {
+    e.outer_tol = o.tol;
+    e.budget = o.max_iter;
+  }
+  WF_TRY(push_states(sw, st, s));
+  tm.start(s);
+  CgState* dst = sw.state.as<CgState>();
+  double* parts = sw.partials.as<double>();
+  WF_HIP(launch_outer_init(sw.x64.as<double>(), sw.r64.as<double>(), sw.b64.as<double>(), g.m, g.m,
+                           parts, dst, nr, s));
+  std::vector<std::vector<double>> hist(nr);
+  int outer = 0;
+  for (;; ++outer) {
+    WF_TRY(sw.pull_state(s));
+    bool any = false;
+    for (int i = 0; i < nr; ++i) {
+      CgState& c = sw.st_host[i];
+      if (c.outer_status != CG_RUNNING) continue;
+      const double rel = c.outer_bnorm > 0 ? std::sqrt(c.outer_rr) / c.outer_bnorm : 0.0;
+      hist[i].push_back(rel);
+      const size_t k = hist[i].size();
+      if (rel <= o.tol || c.budget <= 0) continue;
+      if (k >= 3 && rel > 0.5 * hist[i][k - 3]) {
+        // refinement stagnates: stop this RHS (the caller may rerun in FP64)
+        const int32_t stop = CG_STOPPED;
+        WF_HIP(hipMemcpyAsync(reinterpret_cast<char*>(dst + i) + offsetof(CgState, outer_status),
+                              &stop, sizeof stop, hipMemcpyHostToDevice, s));
+        WF_HIP(hipStreamSynchronize(s));
+        c.outer_status = CG_STOPPED;
+        continue;
+      }
+      any = true;
+    }
+    if (!any || outer >= max_outer) break;
+    Vecs<float> v = v32(sw);
+    WF_HIP(launch_inner_setup(dst, inner_tol, nr, s));
+    WF_HIP(launch_cg_init<float>(v.x, v.r, sw.r64.as<double>(), g.m, g.m, 1, parts, dst, nr, s));
+    WF_TRY(iterate_until_done<float>(od, sw, v, nr, check, s));
+    WF_HIP(launch_inner_finish(dst, nr, s));
+    WF_HIP(launch_refine_add(sw.x64.as<double>(), v.x, g.m, g.m, dst, nr, s));
+    WF_TRY(true_residual(od, sw, sw.r64.as<double>(), nr, s));
+  }
+  const double ms = tm.stop(s);
+  WF_TRY(sw.pull_state(s));
+  for (int i = 0; i < nr; ++i) {
+    const CgState& c = sw.st_host[i];
+    wf_solve_info& in = infos[i];
+    in = wf_solve_info{};
+    in.iters_total = o.max_iter - c.budget;
+    in.outer_steps = c.outer_steps;
+    in.rel_res_recursive = c.rel;
+    const double rel = c.outer_bnorm > 0 ? std::sqrt(c.outer_rr) / c.outer_bnorm : 0.0;
+    in.rel_res_true = rel;
+    in.time_ms = ms;
+    in.model_bytes = (in.iters_total * model_bytes_iteration(false) +
+                      c.outer_steps * (model_bytes_residual() + 36.0) + 24.0) * M;
+    in.nbar = c.nbar;
+    wf_status stt;
+    if (c.outer_status == CG_BREAKDOWN) stt = WF_EBREAKDOWN;
+    else if (rel <= o.tol) stt = WF_OK;
+    else stt = WF_ENOTCONV;
+    in.status = stt;
+    if (severity(stt) > severity(worst.code))
+      worst = fail(stt, std::string("rhs ") + std::to_string(i) + ": " + wf_status_str(stt));
+  }
+  return worst;
+}
+
+// ---- stepwise FP64 solve ---------------------------------------------------
+
+Status fp64_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, double nbar,
+                  const wf_solve_opts& o, hipStream_t s) {
+  WF_TRY(sw.ensure(al, od.g, 1, true, false));
+  std::vector<CgState> st(1);
+  st[0] = CgState{};
+  st[0].nbar = nbar;
+  st[0].tol = o.tol;
+  st[0].max_iter = o.max_iter;
+  WF_TRY(push_states(sw, st, s));
+  Vecs<double> v = v64(sw);
+  WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), od.g.m, od.g.m, 0,
+                                sw.partials.as<double>(), sw.state.as<CgState>(), 1, s));
+  return {};
+}
+
+Status fp64_iterations(const OperatorData& od, SolveWork& sw, int iters, hipStream_t s) {
+  Vecs<double> v = v64(sw);
+  for (int k = 0; k < iters; ++k) WF_TRY(cg_iteration<double>(od, sw, v, 1, s));
+  return {};
+}
+
+Status fp64_finish(const OperatorData& od, SolveWork& sw, hipStream_t s, wf_solve_info* info) {
+  WF_TRY(true_residual(od, sw, sw.q64.as<double>(), 1, s));
+  WF_TRY(sw.pull_state(s));
+  const CgState& c = sw.st_host[0];
+  *info = wf_solve_info{};
+  info->iters_total = c.iter;
+  info->rel_res_recursive = c.bnorm > 0 ? c.rel : 0.0;
+  info->rel_res_true = c.bnorm > 0 ? std::sqrt(c.outer_rr) / c.bnorm : 0.0;
+  info->model_bytes = (c.iter * model_bytes_iteration(true) + model_bytes_residual()) * (double)od.g.m;
+  info->nbar = c.nbar;
+  info->status = c.done ? map_cg_status(c.status) : WF_ENOTCONV;
+  if (info->status != WF_OK)
+    return fail((wf_status)info->status, wf_status_str((wf_status)info->status));
+  return {};
+}
+
+namespace {
+struct SnapHeader {
+  uint64_t magic;
+  int32_t n;
+  int32_t pad;
+  double box;
+};
+constexpr uint64_t SNAP_MAGIC = 0x5746534e41503031ull;  // "WFSNAP01"
+}  // namespace
+
+size_t snapshot_bytes(const Grid& g) {
+  return sizeof(SnapHeader) + sizeof(CgState) + 3 * (size_t)g.m * 8;
+}
+
+Status snapshot_save(const Grid& g, SolveWork& sw, void* buf, hipStream_t s) {
+  char* p = static_cast<char*>(buf);
+  SnapHeader h{SNAP_MAGIC, g.n, 0, g.box};
+  std::memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  WF_HIP(hipMemcpyAsync(p, sw.state.p, sizeof(CgState), hipMemcpyDeviceToHost, s));
+  p += sizeof(CgState);
+  const size_t vb = (size_t)g.m * 8;
+  WF_HIP(hipMemcpyAsync(p, sw.x64.p, vb, hipMemcpyDeviceToHost, s));
+  WF_HIP(hipMemcpyAsync(p + vb, sw.r64.p, vb, hipMemcpyDeviceToHost, s));
+  WF_HIP(hipMemcpyAsync(p + 2 * vb, sw.p64.p, vb, hipMemcpyDeviceToHost, s));
+  WF_HIP(hipStreamSynchronize(s));
+  return {};
+}
+
+Status snapshot_load(const OperatorData& od, const Allocator& al, SolveWork& sw, const void* buf,
+                     hipStream_t s) {
+  const char* p = static_cast<const char*>(buf);
+  SnapHeader h;
+  std::memcpy(&h, p, sizeof h);
+  if (h.magic != SNAP_MAGIC || h.n != od.g.n || h.box != od.g.box)
+    return fail(WF_EINVAL, "snapshot does not match this grid");
+  WF_TRY(sw.ensure(al, od.g, 1, true, false));
+  p += sizeof h;
+  CgState st;
+  std::memcpy(&st, p, sizeof st);
+  st.ticket = 0;
+  WF_HIP(hipMemcpyAsync(sw.state.p, &st, sizeof st, hipMemcpyHostToDevice, s));
+  p += sizeof(CgState);
+  const size_t vb = (size_t)od.g.m * 8;
+  WF_HIP(hipMemcpyAsync(sw.x64.p, p, vb, hipMemcpyHostToDevice, s));
+  WF_HIP(hipMemcpyAsync(sw.r64.p, p + vb, vb, hipMemcpyHostToDevice, s));
+  WF_HIP(hipMemcpyAsync(sw.p64.p, p + 2 * vb, vb, hipMemcpyHostToDevice, s));
+  WF_HIP(hipStreamSynchronize(s));
+  return {};
+}
+
+// ---- multi-RHS batch ---------------------------------------------------------
+
+Status run_batch(const OperatorData& od, const Allocator& al, DepositWork& dw,
+                 const BatchInputs& bi, const wf_solve_opts& o, double* const* s_out,
+                 wf_solve_info* infos, double sumw, hipStream_t s) {
+  const Grid& g = od.g;
+  const int nr = bi.nrhs;
+  SolveWork sw;
+  WF_TRY(sw.ensure(al, g, nr, o.precision == WF_FP64, o.precision == WF_MIXED));
+  DevBuf xyz, nobs, scal, flag;
+  WF_TRY(nobs.ensure(al, (size_t)g.m * 8));
+  WF_TRY(scal.ensure(al, (size_t)(2 + nr) * 8));
+  WF_TRY(flag.ensure(al, 256));
+  WF_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+  WF_HIP(hipMemcpyAsync(scal.p, &sumw, 8, hipMemcpyHostToDevice, s));
+  for (int i = 0; i < nr; ++i) {
+    const double* src = bi.xyz[i];
+    const int64_t ng = bi.n_gal[i];
+    if (bi.mem == WF_HOST) {
+      WF_TRY(xyz.ensure(al, (size_t)std::max<int64_t>(ng, 1) * 24));
+      WF_TRY(upload(xyz.p, bi.xyz[i], (size_t)ng * 24, WF_HOST, s));
+      src = xyz.as<double>();
+    }
+    WF_HIP(launch_check_xyz(src, ng, g.box, flag.as<int>(), s));
+    WF_TRY(run_deposit(al, od, dw, src, ng, bi.scheme, bi.ss, nobs.as<double>(), s));
+    WF_HIP(launch_data_vector(nobs.as<double>(), od.w64.as<double>(), scal.as<double>(), (double)ng,
+                              scal.as<double>() + 2 + i, sw.b64.as<double>() + (size_t)i * g.m, g.m,
+                              s));
+  }
+  dw.fine_spec.release();
+  dw.spec_y.release();
+  dw.spec_c.release();
+  int bad = 0;
+  std::vector<double> nbar(nr);
+  WF_HIP(hipMemcpyAsync(&bad, flag.p, sizeof bad, hipMemcpyDeviceToHost, s));
+  WF_HIP(hipMemcpyAsync(nbar.data(), scal.as<double>() + 2, 8 * (size_t)nr, hipMemcpyDeviceToHost, s));
+  WF_HIP(hipStreamSynchronize(s));
+  if (bad) return fail(WF_EINVAL, "galaxy coordinates must satisfy 0 <= x < L");
+  SolveRequest rq;
+  rq.od = &od;
+  rq.al = &al;
+  rq.work = &sw;
+  rq.nrhs = nr;
+  rq.nbar = nbar.data();
+  rq.opts = o;
+  rq.stream = s;
+  Status r = run_solve(rq, infos);
+  if (r.code == WF_OK || r.code == WF_ENOTCONV || r.code == WF_EBREAKDOWN) {
+    for (int i = 0; i < nr; ++i)
+      WF_TRY(download(s_out[i], sw.x64.as<double>() + (size_t)i * g.m, (size_t)g.m * 8, bi.mem, s));
+    WF_HIP(hipStreamSynchronize(s));
+  }
+  return r;
+}
+
+size_t footprint_bytes(int n, int ss, wf_precision prec, int nrhs) {
+  if (n <= 0 || nrhs <= 0 || (ss != 1 && ss != 2)) return 0;
+  Grid g;
+  g.set(n, 1.0);
+  const double M = (double)g.m, ST = (double)g.spec_total;
+  double op = 12.0 * M + 12.0 * g.lamlen + 24.0 * n;
+  double per = 24.0 * M + 16.0 * ST;                      // b, x, r, spec64
+  per += prec == WF_FP64 ? 16.0 * M : 16.0 * M + 8.0 * ST;  // p, q | 4 FP32 vectors, spec32
+  const int nf = ss * n;
+  double dep = 8.0 * (double)nf * nf * nf + 8.0 * M;  // integer grid, n_obs
+  if (ss == 2)
+    dep += 16.0 * ((double)nf * nf * (n / 2) + (double)nf * n * (n / 2) + ST) + 16.0 * nf;
+  const double parts = 8.0 * std::max<double>((double)g.nrows / 2, 2048.0) * nrhs;
+  return (size_t)(op + per * nrhs + dep + parts + 4096.0 * nrhs);
+}
+
+}  // namespace wf
