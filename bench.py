@@ -1,0 +1,249 @@
+"""Throughput of the Wiener reconstruction on one MI355X.
+
+One step = the whole hot path on one synthetic catalogue with every input
+already in HBM: copy in the galaxies, fixed-point TSC deposit on the 1024^3
+grid, ideal low-pass to 512^3, data vector, and the mixed-precision CG solve
+of the Wiener system (FP32 operator and FFTs, FP64 dots, FP64 residual
+recomputation and iterative refinement) to the refinement tolerance.
+
+Prints one JSON line: solves/s, the roofline figure of the dominant kernel
+(HIP events around its launches during the timed steps), the FP64-CG
+comparison and the oracle timed on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+# Outer (FP64) residual tolerance of the refinement; chosen so that the error
+# against the FP64 oracle solution stays below 1e-6 (the error is a few
+# hundred times the residual on these problems).
+DEFAULT_TOL = 2e-9
+KERNEL_SOURCES = ["paper_0906_3978_amd/csrc/kernels.hip", "paper_0906_3978_amd/csrc/fft.h",
+                  "paper_0906_3978_amd/csrc/common.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(name, n_override=None):
+    import synth
+    wl = synth.workload(name, n=n_override)
+    t = time.perf_counter()
+    ptab = wl.ptab()
+    w = wl.mask()
+    cat = wl.catalogue(ptab, w)
+    log(f"[bench] inputs {wl.name} n={wl.n} ngal={len(cat.xyz)} sigma_G^2={cat.sigma_g2:.2f} "
+        f"({time.perf_counter() - t:.1f} s)")
+    return wl, ptab, w, cat
+
+
+def cpu_baseline(wl, ptab, w, n_gal, iters_fp64, sample_iters=3):
+    """The oracle's plain CG on the same system, timed on the host cores over a
+    few iterations and scaled to a whole FP64 solve of `iters_fp64`
+    iterations (the oracle's algorithm)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import wiener as ow
+    nbar = ow.mean_density(n_gal, w)
+    system = ow.System(wl.n, wl.box, w, ptab, nbar)
+    rng = np.random.Generator(np.random.PCG64(7))
+    b = np.where(w > 0, rng.standard_normal(w.shape), 0.0)
+    with threadpool_limits(1):
+        ow.cg(system, b, 0.0, 1)  # warm the FFT plan cache
+        t = time.perf_counter()
+        ow.cg(system, b, 0.0, sample_iters)
+        dt = (time.perf_counter() - t) / sample_iters
+    per_solve = dt * iters_fp64
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{sample_iters} plain-CG iterations of the FP64 numpy oracle on the "
+                       f"{wl.n}^3 system ({dt:.2f} s/iteration, one core) scaled to the "
+                       f"{iters_fp64} iterations of one FP64 solve; gridding not included")}
+
+
+def traffic_for(kernel, launch_bytes):
+    """HBM bytes per launch from committed rocprofv3 PMC counters, if they were
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    ent = t.get(kernel)
+    if not ent or ent.get("kernel_hash") != kernel_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="bbks512")
+    ap.add_argument("--n", type=int, default=None, help="override the grid size (testing)")
+    ap.add_argument("--tol", type=float, default=DEFAULT_TOL)
+    ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build measures one GPU: the Wiener solve of one grid "
+                          "runs on a single MI355X; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_0906_3978_amd as wf
+
+    wl, ptab, w, cat = make_inputs(args.workload, args.n)
+    n = wl.n
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = wf.Context(0)
+    xyz_d = torch.from_numpy(cat.xyz).to(dev)
+    w_d = torch.from_numpy(w).to(dev)
+    p_d = torch.from_numpy(ptab).to(dev)
+    out = torch.empty((n, n, n), dtype=torch.float64, device=dev)
+    ctx.set_grid(n, wl.box)
+    ctx.set_mask(w_d)
+    ctx.set_power(p_d)
+    torch.cuda.synchronize()
+
+    solve_kw = dict(precision="mixed", tol=args.tol, max_iter=100000, inner_tol=args.inner_tol)
+
+    def step():
+        ctx.set_galaxies(xyz_d)
+        ctx.deposit(wl.scheme, wl.supersample)
+        _, info = ctx.solve(out=out, **solve_kw)
+        return info
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        info = step()
+        log(f"[bench] warmup {i}: {time.perf_counter() - t:.3f} s, iters={info.iters_total} "
+            f"outer={info.outer_steps} rel_res_true={info.rel_res_true:.2e}")
+
+    if not args.no_profile:
+        ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    lat = []
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        infos.append(step())
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_read() if not args.no_profile else {}
+    ctx.profile_enable(False)
+    value = args.steps / elapsed
+    info = infos[-1]
+    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s: {value:.4f} solves/s; "
+        f"iters={info.iters_total} outer={info.outer_steps} rel_res_true={info.rel_res_true:.2e}")
+
+    roofline = None
+    per_kernel = {}
+    if prof:
+        for k, v in prof.items():
+            per_kernel[k] = dict(launches=v["launches"], avg_us=1e3 * v["ms"] / v["launches"],
+                                 gbs=v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None)
+        solve_kernels = {k: v for k, v in prof.items() if k not in ("deposit", "supersample")}
+        dom = max(solve_kernels, key=lambda k: solve_kernels[k]["ms"])
+        d = prof[dom]
+        bpl = d["bytes"] / d["launches"]
+        avg_s = d["ms"] * 1e-3 / d["launches"]
+        ach = bpl / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": traffic_for(dom, bpl), "algorithmic_bytes_per_launch": bpl,
+                    "avg_launch_us": round(avg_s * 1e6, 2)}
+        # whole-iteration figure: the five sweeps + update of the FP32 inner CG
+        it_keys = ["zfwd_f32", "yfwd_f32", "xlam_f32", "yinv_f32", "zinv_f32", "update_f32"]
+        if all(k in prof for k in it_keys):
+            it_ms = sum(prof[k]["ms"] / prof[k]["launches"] for k in it_keys)
+            it_b = sum(prof[k]["bytes"] / prof[k]["launches"] for k in it_keys)
+            roofline["iteration"] = {"ms": round(it_ms, 4), "bytes": it_b,
+                                     "achieved": round(it_b / (it_ms * 1e-3) / 1e9, 1),
+                                     "frac": round(it_b / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                     "bytes_per_cell": round(it_b / n ** 3, 2)}
+
+    fp64 = None
+    if not args.no_fp64:
+        ctx.set_galaxies(xyz_d)
+        ctx.deposit(wl.scheme, wl.supersample)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, inf64 = ctx.solve(out=out, precision="fp64", tol=args.tol, max_iter=100000)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t
+        fp64 = {"solve_s": round(t64, 4), "solves_per_s_solve_only": round(1.0 / t64, 4),
+                "iters": inf64.iters_total, "rel_res_true": inf64.rel_res_true,
+                "mixed_solve_s": round(info.time_ms * 1e-3, 4),
+                "speedup_mixed_over_fp64_solve": round(t64 / (info.time_ms * 1e-3), 3)}
+        log(f"[bench] fp64 solve {t64:.3f} s iters={inf64.iters_total}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        iters_ref = fp64["iters"] if fp64 else info.iters_total
+        t = time.perf_counter()
+        cpu = cpu_baseline(wl, ptab, w, len(cat.xyz), iters_ref)
+        log(f"[bench] cpu baseline {cpu['value']:.3e} solves/s ({time.perf_counter() - t:.1f} s)")
+
+    lat_ms = sorted(1e3 * x for x in lat)
+    res = {
+        "metric": "Wiener-CG solves/s at 512^3 to 1e-6 rel. L2 (mixed vs FP64); p50/p99 latency",
+        "value": round(value, 5),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {n}^3 grid, {wl.box:.0f} Mpc box, BBKS prior, "
+                               f"60 deg cap x exp(-r/150 Mpc), {len(cat.xyz)} lognormal-Poisson "
+                               f"galaxies, {wl.scheme.upper()} deposit 2x supersampled, "
+                               f"mixed-precision CG to FP64 residual {args.tol:g}",
+                   "n": n, "box_mpc": wl.box, "n_gal": int(len(cat.xyz)),
+                   "scheme": wl.scheme, "supersample": wl.supersample,
+                   "tol_outer": args.tol, "iters": info.iters_total,
+                   "outer_steps": info.outer_steps, "rel_res_true": info.rel_res_true},
+        "latency_ms": {"p50": round(lat_ms[len(lat_ms) // 2], 3),
+                       "p99": round(lat_ms[min(len(lat_ms) - 1, math.ceil(0.99 * len(lat_ms)) - 1)], 3)},
+        "roofline": roofline,
+        "kernels": per_kernel,
+        "fp64": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

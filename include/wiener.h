@@ -74,7 +74,8 @@ typedef enum { WF_NGP = 0, WF_CIC = 1, WF_TSC = 2 } wf_scheme;
 
 typedef enum {
   WF_FP64 = 0,   /* FP64 vectors, FFTs and reductions                          */
-  WF_MIXED = 1   /* FP32 inner CG (FP64 dots) inside FP64 iterative refinement */
+  WF_MIXED = 1   /* FP32 operator and vectors, FP64 dots, FP64 residual
+                    recomputation and solution (reliable-update refinement) */
 } wf_precision;
 
 /* Device allocator callbacks (e.g. a framework's caching allocator).  alloc
@@ -88,13 +89,15 @@ typedef struct wf_server wf_server;
 
 /* Solver options.
  *   tol         stop when ||b - A x|| / ||b|| <= tol.  FP64: on the recursive
- *               CG residual.  MIXED: on the FP64 residual recomputed after
- *               each refinement step.  tol = 0 runs exactly max_iter CG
- *               iterations (FP64).
- *   max_iter    FP64: CG iterations.  MIXED: total inner iterations.
- *   inner_tol   MIXED only: relative residual reduction of each inner FP32 CG
- *               solve (e.g. 1e-4).  0 selects the default.
- *   max_outer   MIXED only: refinement steps (0 selects the default, 16).
+ *               CG residual.  MIXED: on the residual recomputed with the FP64
+ *               operator.  tol = 0 runs exactly max_iter iterations.
+ *   max_iter    CG iterations (MIXED: FP32 iterations).
+ *   inner_tol   MIXED only: reliable-update factor.  The FP32 correction is
+ *               folded into the FP64 solution and the residual recomputed in
+ *               FP64 each time the FP32 recursive residual has dropped by this
+ *               factor since the previous recomputation (0: default 0.1).
+ *   max_outer   MIXED only: maximum number of FP64 residual recomputations
+ *               (0: no limit).
  *   check_every host convergence checks every this many iterations (0: 16).
  *               Results do not depend on it: the device stops iterating at
  *               convergence by itself. */
@@ -108,9 +111,9 @@ typedef struct {
 } wf_solve_opts;
 
 typedef struct {
-  int32_t iters_total;        /* CG iterations (MIXED: sum of inner)          */
-  int32_t outer_steps;        /* MIXED refinement steps (FP64: 0)             */
-  double rel_res_recursive;   /* last recursive residual of the (inner) CG    */
+  int32_t iters_total;        /* CG iterations                                */
+  int32_t outer_steps;        /* MIXED: FP64 residual recomputations          */
+  double rel_res_recursive;   /* last recursive residual ||r|| / ||b||        */
   double rel_res_true;        /* ||b - A x|| / ||b|| with the FP64 operator   */
   double time_ms;             /* wall time of the solve on the device         */
   double model_bytes;         /* algorithmic HBM bytes moved by the solve     */
@@ -211,6 +214,33 @@ wf_status wf_solve_batch(wf_ctx* ctx, int32_t nrhs, const double* const* xyz,
                          int32_t supersample, const wf_solve_opts* opts,
                          double* const* s_out, wf_mem mem,
                          wf_solve_info* infos);
+
+/* ---- live kernel timing ------------------------------------------------ */
+/* Kernel classes timed by the profiler: the five sweeps of one operator
+ * application and the CG vector update, in FP32 (0..5) and FP64 (6..11),
+ * then the gridding kernels. */
+#define WF_PROF_KINDS 14
+typedef enum {
+  WF_PROF_ZFWD_F32 = 0, WF_PROF_YFWD_F32, WF_PROF_XLAM_F32, WF_PROF_YINV_F32,
+  WF_PROF_ZINV_F32, WF_PROF_UPDATE_F32,
+  WF_PROF_ZFWD_F64, WF_PROF_YFWD_F64, WF_PROF_XLAM_F64, WF_PROF_YINV_F64,
+  WF_PROF_ZINV_F64, WF_PROF_UPDATE_F64,
+  WF_PROF_DEPOSIT, WF_PROF_SUPERSAMPLE
+} wf_prof_kind;
+
+/* Per class: launches, summed device time (HIP events recorded on the
+ * context's stream around every launch) and algorithmic HBM bytes (the bytes
+ * the pass must read and write once: inputs, outputs, the half spectrum). */
+typedef struct {
+  int64_t launches[WF_PROF_KINDS];
+  double ms[WF_PROF_KINDS];
+  double bytes[WF_PROF_KINDS];
+} wf_profile;
+
+/* Turns event timing on (1) or off (0) and clears the counters. */
+wf_status wf_profile_enable(wf_ctx* ctx, int32_t on);
+/* Synchronises the stream and returns the counters since enabling. */
+wf_status wf_profile_read(wf_ctx* ctx, wf_profile* out);
 
 /* Device bytes one solve needs at the peak of its phases (deposit or solve). */
 size_t wf_footprint_bytes(int32_t n, int32_t supersample, wf_precision prec,

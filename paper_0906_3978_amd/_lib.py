@@ -50,6 +50,22 @@ class Request(C.Structure):
                 ("scheme", C.c_int), ("supersample", C.c_int32), ("opts", SolveOpts)]
 
 
+PROF_KINDS = 14
+PROF_NAMES = ["zfwd_f32", "yfwd_f32", "xlam_f32", "yinv_f32", "zinv_f32", "update_f32",
+              "zfwd_f64", "yfwd_f64", "xlam_f64", "yinv_f64", "zinv_f64", "update_f64",
+              "deposit", "supersample"]
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * PROF_KINDS), ("ms", C.c_double * PROF_KINDS),
+                ("bytes", C.c_double * PROF_KINDS)]
+
+    def as_dict(self):
+        return {PROF_NAMES[k]: dict(launches=int(self.launches[k]), ms=float(self.ms[k]),
+                                    bytes=float(self.bytes[k]))
+                for k in range(PROF_KINDS) if self.launches[k]}
+
+
 class ServerStats(C.Structure):
     _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("solves_per_s", C.c_double),
                 ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("peak_bytes", C.c_size_t)]
@@ -92,6 +108,8 @@ SIGNATURES = {
                                  _I32, C.POINTER(SolveOpts), C.POINTER(C.c_void_p), C.c_int,
                                  C.POINTER(SolveInfo)]),
     "wf_footprint_bytes": (_SZ, [_I32, _I32, C.c_int, _I32]),
+    "wf_profile_enable": (C.c_int, [_V, _I32]),
+    "wf_profile_read": (C.c_int, [_V, C.POINTER(Profile)]),
     "wf_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, _SZ, _I32, ALLOC_FN, FREE_FN, _V]),
     "wf_server_submit": (C.c_int, [_V, C.POINTER(Request), C.POINTER(C.c_uint64)]),
     "wf_server_poll": (C.c_int, [_V, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(SolveInfo)]),
@@ -107,6 +125,13 @@ def lib():
     """Loads libwiener.so; raises if it has not been built (no fallback)."""
     global _LIB
     if _LIB is None:
+        # torch ships its own HIP runtime under the same soname; load it first
+        # so that the process holds exactly one runtime whichever module the
+        # caller imported first.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_0906_3978_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -306,6 +331,14 @@ class Context:
         si = SolveInfo()
         self._check(self._L.wf_solve_finish(self._h, out.ctypes.data, WF_HOST, C.byref(si)), ok=allow)
         return out, _info(si)
+
+    def profile_enable(self, on=True):
+        self._check(self._L.wf_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        pr = Profile()
+        self._check(self._L.wf_profile_read(self._h, C.byref(pr)))
+        return pr.as_dict()
 
     def solve_batch(self, catalogues, scheme="cic", supersample=2, outs=None,
                     allow=(WF_OK,), **kw):

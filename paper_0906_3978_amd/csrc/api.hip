@@ -27,6 +27,7 @@ struct wf_ctx {
   bool solve_active = false;
   wf_solve_opts active_opts{};
   double active_ms = 0.0;
+  Profiler prof;
 };
 
 namespace {
@@ -328,13 +329,13 @@ wf_status wf_apply_operator(wf_ctx* c, wf_precision prec, const double* v, doubl
       WF_TRY(operator_passes<double>(c->od, ZIN_REAL, sw.x64.as<double>(), nullptr,
                                      sw.spec64.as<double2>(), ZOUT_APPLY, sw.q64.as<double>(),
                                      sw.x64.as<double>(), nullptr, sw.state.as<CgState>(),
-                                     sw.partials.as<double>(), 1, false, c->stream));
+                                     sw.partials.as<double>(), 1, SKIP_NONE, c->stream));
     } else {
       WF_HIP(launch_f64_to_f32(sw.x32.as<float>(), sw.x64.as<double>(), g.m, c->stream));
       WF_TRY(operator_passes<float>(c->od, ZIN_REAL, sw.x32.as<float>(), nullptr,
                                     sw.spec32.as<float2>(), ZOUT_APPLY, sw.q32.as<float>(),
                                     sw.x32.as<float>(), nullptr, sw.state.as<CgState>(),
-                                    sw.partials.as<double>(), 1, false, c->stream));
+                                    sw.partials.as<double>(), 1, SKIP_NONE, c->stream));
       WF_HIP(launch_f32_to_f64(sw.q64.as<double>(), sw.q32.as<float>(), g.m, c->stream));
     }
     WF_TRY(download(av, sw.q64.p, (size_t)g.m * 8, mem, c->stream));
@@ -524,6 +525,32 @@ wf_status wf_solve_batch(wf_ctx* c, int32_t nrhs, const double* const* xyz, cons
   c->have_rhs = false;
   c->solve_active = false;
   return finish(c, s);
+}
+
+wf_status wf_profile_enable(wf_ctx* c, int32_t on) {
+  if (!c) return WF_EINVAL;
+  Status s = set_device(c);
+  if (!s.ok()) return finish(c, s);
+  (void)hipStreamSynchronize(c->stream);
+  c->prof.harvest();
+  c->prof.clear();
+  c->prof.on = on != 0;
+  c->od.prof = c->prof.on ? &c->prof : nullptr;
+  return WF_OK;
+}
+
+wf_status wf_profile_read(wf_ctx* c, wf_profile* out) {
+  if (!c || !out) return c ? finish(c, fail(WF_EINVAL, "null output")) : WF_EINVAL;
+  Status s = set_device(c);
+  if (!s.ok()) return finish(c, s);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return finish(c, fail(WF_EDEVICE, "sync failed"));
+  c->prof.harvest();
+  for (int k = 0; k < WF_PROF_KINDS; ++k) {
+    out->launches[k] = c->prof.launches[k];
+    out->ms[k] = c->prof.ms[k];
+    out->bytes[k] = c->prof.bytes[k];
+  }
+  return WF_OK;
 }
 
 size_t wf_footprint_bytes(int32_t n, int32_t ss, wf_precision prec, int32_t nrhs) {

@@ -34,29 +34,42 @@ template <int DIR, typename V> __device__ __forceinline__ V mul_i(V a) {
 // the host may enqueue iterations ahead of its convergence checks.
 // ---------------------------------------------------------------------------
 struct CgState {
-  double rho;        // r.r of the current residual
-  double bnorm;      // ||b|| of the system being iterated (inner: ||r_outer||-scaled rhs)
-  double tol;        // stop when sqrt(rho)/bnorm <= tol
+  double rho;        // r.r of the current (recursive) residual
+  double rho_old;    // r.r of the previous iteration
+  double bnorm;      // ||b||
+  double tol;        // stop when ||r|| / ||b|| <= tol
   double alpha, beta, pq;
-  double rel;        // last sqrt(rho)/bnorm
+  double rel;        // last ||r|| / ||b|| (recursive)
   double nbar;       // mean density per cell of this right-hand side
-  double outer_rr;   // FP64 residual norm^2 of the refinement loop
-  double outer_bnorm;
-  double scale;      // 1/||r_outer|| used to normalise the inner rhs
-  int32_t iter;      // completed CG iterations (this inner solve)
+  double outer_rr;   // ||b - A64 x64||^2 from the last FP64 residual
+  double rmax;       // reliable updates: ||r|| right after the last update
+  double delta;      // reliable updates: update once ||r|| <= delta * rmax
+  int32_t iter;      // completed CG iterations
   int32_t max_iter;
-  int32_t done;      // 1: converged / max_iter / breakdown
-  int32_t status;    // 0 running, 1 converged, 2 max_iter, 3 breakdown
-  int32_t first;     // 1: next p-update is p = r
-  int32_t total_iter;// across inner solves
+  int32_t done;      // 1: iteration stopped (converged, max_iter, breakdown, update due)
+  int32_t status;    // CG_* below
+  int32_t first;     // 1: next direction update is p = r
+  int32_t reliable;  // 1: FP32 CG with FP64 reliable updates
   uint32_t ticket;   // last-block counter of the reductions
-  int32_t budget;    // refinement: inner iterations still allowed
-  double outer_tol;  // refinement: stop when sqrt(outer_rr)/outer_bnorm <= outer_tol
-  int32_t outer_status;  // refinement: 0 running, 1 converged, 2 budget spent, 3 breakdown, 4 stopped
-  int32_t outer_steps;
+  int32_t updates;   // reliable updates done
+  int32_t max_updates;
+  int32_t pad;
 };
 
-enum : int32_t { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN = 3, CG_STOPPED = 4 };
+enum : int32_t {
+  CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN = 3, CG_STOPPED = 4,
+  CG_UPDATE = 5   // reliable update due: fold x into FP64, recompute the residual
+};
+
+// Which right-hand sides a launch skips: none, those whose iteration has
+// stopped, or all but those waiting for a reliable update.
+enum : int32_t { SKIP_NONE = 0, SKIP_DONE = 1, SKIP_UNLESS_UPDATE = 2 };
+
+__device__ __forceinline__ bool skip_rhs(const CgState* st, int mode) {
+  if (mode == SKIP_DONE) return st->done != 0;
+  if (mode == SKIP_UNLESS_UPDATE) return st->status != CG_UPDATE;
+  return false;
+}
 
 // Coherent (device-scope) load of a value written by another workgroup of
 // the same kernel before its release fence.
@@ -104,12 +117,35 @@ __device__ __forceinline__ bool publish_partial(double part, double* partials,
   return last;
 }
 
+// Two partial sums per block (stored interleaved).
+__device__ __forceinline__ bool publish_partial2(double a, double b, double* partials,
+                                                 uint32_t* ticket, uint32_t nblocks, int* flag) {
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = a;
+    partials[2 * blockIdx.x + 1] = b;
+    __threadfence();
+    uint32_t t = atomicAdd(ticket, 1u);
+    *flag = (t == nblocks - 1);
+  }
+  __syncthreads();
+  bool last = *flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
 // Deterministic sum of partials[0..n): each thread sums a fixed strided
 // subset, then a fixed tree.
 __device__ __forceinline__ double reduce_partials(const double* partials, uint32_t n,
                                                   double* sh) {
   double s = 0.0;
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s += load_agent(partials + i);
+  return block_sum(s, sh);
+}
+
+__device__ __forceinline__ double reduce_partials_strided(const double* partials, uint32_t n,
+                                                          int stride, double* sh) {
+  double s = 0.0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s += load_agent(partials + (size_t)i * stride);
   return block_sum(s, sh);
 }
 

@@ -41,6 +41,58 @@ Status DevBuf::ensure(const Allocator& al, size_t b) {
   return {};
 }
 
+Profiler::~Profiler() {
+  for (auto& pr : pending) {
+    (void)hipEventDestroy(pr.a);
+    (void)hipEventDestroy(pr.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+void Profiler::clear() {
+  for (int k = 0; k < WF_PROF_KINDS; ++k) {
+    launches[k] = 0;
+    ms[k] = 0.0;
+    bytes[k] = 0.0;
+  }
+}
+
+int Profiler::begin(int kind, double b, hipStream_t s) {
+  if (!on) return -1;
+  if (pending.size() >= 8192) {
+    (void)hipStreamSynchronize(s);
+    harvest();
+  }
+  hipEvent_t e[2];
+  for (auto& x : e) {
+    if (!pool.empty()) {
+      x = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&x) != hipSuccess) {
+      return -1;
+    }
+  }
+  (void)hipEventRecord(e[0], s);
+  pending.push_back(Pair{e[0], e[1], kind, b});
+  return (int)pending.size() - 1;
+}
+
+void Profiler::end(int idx, hipStream_t s) { (void)hipEventRecord(pending[idx].b, s); }
+
+void Profiler::harvest() {
+  for (auto& pr : pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pr.a, pr.b) == hipSuccess) {
+      launches[pr.kind] += 1;
+      ms[pr.kind] += t;
+      bytes[pr.kind] += pr.bytes;
+    }
+    pool.push_back(pr.a);
+    pool.push_back(pr.b);
+  }
+  pending.clear();
+}
+
 void Grid::set(int n_, double box_) {
   n = n_;
   box = box_;
@@ -76,7 +128,7 @@ Status SolveWork::ensure(const Allocator& al, const Grid& g, int nr, bool fp64_c
   }
   // partials: enough for the largest grid of any reduction kernel per RHS
   const int64_t zblocks = g.nrows / 2;  // upper bound of z-pass blocks (NB >= 1)
-  const int64_t per = std::max<int64_t>(zblocks, 2048);
+  const int64_t per = std::max<int64_t>(zblocks, 4096);
   WF_TRY(partials.ensure(al, (size_t)per * nr * 8));
   WF_TRY(state.ensure(al, sizeof(CgState) * nr));
   if (st_cap < nr) {
@@ -210,7 +262,8 @@ template <typename T> static const T* w_of(const OperatorData& od) {
 }
 
 template <typename T>
-static StrArgs<T> str_args(const OperatorData& od, cplx<T>* spec, bool xpass, const CgState* st) {
+static StrArgs<T> str_args(const OperatorData& od, cplx<T>* spec, bool xpass, const CgState* st,
+                           int skip) {
   const Grid& g = od.g;
   const int tb = strided_tb(g.n, sizeof(T) == 8);
   cplx<T>* nyq = spec + g.spec_main;
@@ -221,15 +274,19 @@ static StrArgs<T> str_args(const OperatorData& od, cplx<T>* spec, bool xpass, co
   a.nblk1 = a.s1.n_outer * a.s1.n_btiles;
   a.lam = lam_of<T>(od);
   a.tw = tw_of<T>(od);
-  a.st = st;
+  a.st = skip != SKIP_NONE ? st : nullptr;
+  a.skip = skip;
   return a;
 }
 
 template <typename T>
 Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T* p,
                        cplx<T>* spec, int zout_mode, T* out, const T* aux, const double* bvec,
-                       CgState* st, double* partials, int nrhs, bool check_done, hipStream_t s) {
+                       CgState* st, double* partials, int nrhs, int skip, hipStream_t s) {
   const Grid& g = od.g;
+  const int kbase = sizeof(T) == 8 ? WF_PROF_ZFWD_F64 : WF_PROF_ZFWD_F32;
+  const double vb = (double)sizeof(T) * g.m * nrhs;                 // one real vector
+  const double sb = 2.0 * sizeof(T) * g.spec_total * nrhs;         // one half spectrum
   ZfwdArgs<T> zf{};
   zf.in = in_or_r;
   zf.p = p;
@@ -240,14 +297,24 @@ Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T
   zf.rhs_main = g.spec_total;
   zf.rhs_nyq = g.spec_total;
   zf.tw = tw_of<T>(od);
-  zf.st = (zin_mode == ZIN_CGP) ? st : nullptr;
-  WF_HIP(launch_zfwd<T>(g.n, zin_mode, zf, g.nrows, nrhs, s));
-
-  const CgState* sc = check_done ? st : nullptr;
-  WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, false, sc), nrhs, s));
-  WF_HIP(launch_strided<T>(g.n, SM_FWD_LAM_INV, str_args<T>(od, spec, true, sc), nrhs, s));
-  WF_HIP(launch_strided<T>(g.n, SM_INV, str_args<T>(od, spec, false, sc), nrhs, s));
-
+  zf.st = (zin_mode == ZIN_CGP || skip != SKIP_NONE) ? st : nullptr;
+  zf.skip = skip;
+  {
+    ProfScope ps(od.prof, kbase + 0, (zin_mode == ZIN_CGP ? 3 * vb : vb) + sb, s);
+    WF_HIP(launch_zfwd<T>(g.n, zin_mode, zf, g.nrows, nrhs, s));
+  }
+  {
+    ProfScope ps(od.prof, kbase + 1, 2 * sb, s);
+    WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, false, st, skip), nrhs, s));
+  }
+  {
+    ProfScope ps(od.prof, kbase + 2, 2 * sb, s);
+    WF_HIP(launch_strided<T>(g.n, SM_FWD_LAM_INV, str_args<T>(od, spec, true, st, skip), nrhs, s));
+  }
+  {
+    ProfScope ps(od.prof, kbase + 3, 2 * sb, s);
+    WF_HIP(launch_strided<T>(g.n, SM_INV, str_args<T>(od, spec, false, st, skip), nrhs, s));
+  }
   ZinvArgs<T> zi{};
   zi.in_main = spec;
   zi.in_nyq = spec + g.spec_main;
@@ -264,16 +331,29 @@ Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T
   zi.partials = partials;
   zi.tw = tw_of<T>(od);
   zi.st = st;
-  WF_HIP(launch_zinv<T>(g.n, zout_mode, zi, g.nrows, nrhs, s));
+  zi.skip = skip;
+  {
+    // spectrum in; aux and w in (w once for all RHS); result out; RES also reads b
+    const double wb = (double)sizeof(T) * g.m;
+    double zb = sb + 2 * vb + wb;
+    if (zout_mode == ZOUT_RES) zb += 8.0 * g.m * nrhs;
+    {
+      ProfScope ps(od.prof, kbase + 4, zb, s);
+      WF_HIP(launch_zinv<T>(g.n, zout_mode, zi, g.nrows, nrhs, s));
+    }
+    if (zout_mode == ZOUT_CGQ || zout_mode == ZOUT_RES)
+      WF_HIP(launch_finalize(zout_mode == ZOUT_CGQ ? FIN_PQ : FIN_RES, partials,
+                             zpass_blocks(g.n, g.nrows, sizeof(T) == 8), skip, st, nrhs, s));
+  }
   return {};
 }
 
 template Status operator_passes<float>(const OperatorData&, int, const float*, float*, cplx<float>*,
                                        int, float*, const float*, const double*, CgState*, double*,
-                                       int, bool, hipStream_t);
+                                       int, int, hipStream_t);
 template Status operator_passes<double>(const OperatorData&, int, const double*, double*,
                                         cplx<double>*, int, double*, const double*, const double*,
-                                        CgState*, double*, int, bool, hipStream_t);
+                                        CgState*, double*, int, int, hipStream_t);
 
 template <typename T>
 Status forward_passes(const OperatorData& od, const T* in, cplx<T>* spec, hipStream_t s) {
@@ -288,8 +368,8 @@ Status forward_passes(const OperatorData& od, const T* in, cplx<T>* spec, hipStr
   zf.rhs_nyq = g.spec_total;
   zf.tw = tw_of<T>(od);
   WF_HIP(launch_zfwd<T>(g.n, ZIN_REAL, zf, g.nrows, 1, s));
-  WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, false, nullptr), 1, s));
-  WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, true, nullptr), 1, s));
+  WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, false, nullptr, SKIP_NONE), 1, s));
+  WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, true, nullptr, SKIP_NONE), 1, s));
   return {};
 }
 template Status forward_passes<float>(const OperatorData&, const float*, cplx<float>*, hipStream_t);
@@ -307,9 +387,13 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
   const int64_t mf = (int64_t)nf * nf * nf;
   WF_TRY(dw.grid.ensure(al, (size_t)mf * 8));
   long long* grid = dw.grid.as<long long>();
-  WF_HIP(launch_fill_i64(grid, mf, s));
   const double c = (double)nf / g.box;
-  WF_HIP(launch_deposit(scheme, xyz, ngal, c, nf, grid, s));
+  {
+    const int st = scheme == WF_NGP ? 1 : (scheme == WF_CIC ? 8 : 27);
+    ProfScope ps(od.prof, WF_PROF_DEPOSIT, 8.0 * mf + 24.0 * ngal + 16.0 * st * ngal, s);
+    WF_HIP(launch_fill_i64(grid, mf, s));
+    WF_HIP(launch_deposit(scheme, xyz, ngal, c, nf, grid, s));
+  }
   const double unit = scheme == WF_NGP ? 1.0 : std::ldexp(1.0, -39);
   if (ss == 1) {
     WF_HIP(launch_i64_to_f64(nobs, grid, unit, g.m, s));
@@ -317,6 +401,10 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
   }
   // fine forward transform, keeping kz < n/2
   const int h = n / 2;
+  ProfScope pss(od.prof, WF_PROF_SUPERSAMPLE,
+                8.0 * mf + 2 * 16.0 * nf * nf * h + 2 * 16.0 * nf * n * h + 16.0 * g.spec_total * 5 +
+                    8.0 * g.m,
+                s);
   if (dw.tw_fine.bytes < (size_t)nf * 16) WF_TRY(make_twiddles(al, nf, dw.tw_fine, nullptr));
   const int64_t fine_spec = (int64_t)nf * nf * h;
   WF_TRY(dw.fine_spec.ensure(al, (size_t)fine_spec * 16));
@@ -380,8 +468,8 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
   // the target Nyquist planes are dropped
   WF_HIP(launch_fill_c64(sc + g.spec_main, (int64_t)n * n, s));
   // coarse inverse: x, y, then z to real with 1/n^3
-  WF_HIP(launch_strided<double>(n, SM_INV, str_args<double>(od, sc, true, nullptr), 1, s));
-  WF_HIP(launch_strided<double>(n, SM_INV, str_args<double>(od, sc, false, nullptr), 1, s));
+  WF_HIP(launch_strided<double>(n, SM_INV, str_args<double>(od, sc, true, nullptr, SKIP_NONE), 1, s));
+  WF_HIP(launch_strided<double>(n, SM_INV, str_args<double>(od, sc, false, nullptr, SKIP_NONE), 1, s));
   ZinvArgs<double> zi{};
   zi.in_main = sc;
   zi.in_nyq = sc + g.spec_main;

@@ -1,0 +1,653 @@
+// The five sweeps of the Wiener operator A p = F^-1 Lambda F p + nbar w p
+// (eq:WF with the LSQ noise of eq:noiseav) on gfx950:
+//   1. z pass : real rows -> half spectrum (two real rows per complex FFT),
+//               fused with the CG direction update p = r + beta p;
+//   2. y pass : forward FFT along y (tiles of TB adjacent kz columns);
+//   3. x pass : forward FFT along x, multiply by Lambda[|m|^2], inverse FFT;
+//   4. y pass : inverse FFT along y;
+//   5. z pass : half spectrum -> real rows, fused with + nbar w p and the
+//               block partial of p.q.
+// The half spectrum is stored as main[x][y][kz < N/2] plus the kz = N/2
+// plane nyq[x][y], so every strided tile covers an aligned run of columns.
+// Global memory is moved in 16-byte vectors, all loads of a thread issued
+// before their first use.  Block partials of the reductions are summed in a
+// fixed order by a one-block finalize kernel per right-hand side.
+#include "fft.h"
+#include "launch.h"
+
+namespace wf {
+
+constexpr int NT = 256;
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <typename T> using vec16 = typename Vec16<T>::type;
+
+template <typename T> __device__ __forceinline__ vec16<T> ld16(const T* p) {
+  return *reinterpret_cast<const vec16<T>*>(p);
+}
+template <typename T> __device__ __forceinline__ void st16(T* p, vec16<T> v) {
+  *reinterpret_cast<vec16<T>*>(p) = v;
+}
+
+// ---------------------------------------------------------------------------
+// tile geometry
+// ---------------------------------------------------------------------------
+template <typename T, int N> constexpr int z_nb() {
+  const int elems = (sizeof(T) == 8) ? 2048 : 4096;  // 32 KB of LDS per block
+  int lim = elems / N;
+  if (lim < 1) lim = 1;
+  const int pairs = N * N / 2;
+  for (int d = lim; d >= 1; --d)
+    if (pairs % d == 0) return d;
+  return 1;
+}
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+
+template <typename T, int N> constexpr int str_tb() {
+  const int cap = 65536 / (N * (int)sizeof(cplx<T>));
+  int p = 1;
+  while (p * 2 <= cap && p < 16) p *= 2;
+  return cgcd(p, N / 4);
+}
+
+__device__ __forceinline__ int signed_m(int i, int n) { return i < (n >> 1) ? i : i - n; }
+
+// ---------------------------------------------------------------------------
+// z forward: real rows -> half spectrum
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_zfwd(ZfwdArgs<T> a) {
+  using V = cplx<T>;
+  using R = vec16<T>;
+  constexpr int RW = 16 / sizeof(T);   // reals per vector
+  constexpr int CW = 16 / sizeof(V);   // complex values per vector
+  constexpr int NB = z_nb<T, N>();
+  constexpr int H = N / 2;
+  constexpr int ITEMS = NB * N / RW;
+  constexpr int PER = (ITEMS + NT - 1) / NT;
+  __shared__ __align__(16) V lds[NB * N];
+  const int rhs = blockIdx.y;
+  CgState* st = a.st ? a.st + rhs : nullptr;
+  if (st && skip_rhs(st, a.skip)) return;
+  const int64_t row0 = (int64_t)blockIdx.x * NB * 2;
+
+  T beta = T(0);
+  bool first = true;
+  if constexpr (MODE == ZIN_CGP) {
+    first = st->first != 0;
+    beta = (T)st->beta;
+  }
+  R va[PER], vb[PER];
+#pragma unroll
+  for (int c = 0; c < PER; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (ITEMS % NT == 0 || q < ITEMS) {
+      const int b = q / (N / RW), z = (q - b * (N / RW)) * RW;
+      const int64_t i0 = (row0 + 2 * b) * N + z;
+      if constexpr (MODE == ZIN_REAL) {
+        const T* in = a.in + rhs * a.rhs_in;
+        va[c] = ld16(in + i0);
+        vb[c] = ld16(in + i0 + N);
+      } else if constexpr (MODE == ZIN_CGP) {
+        const T* r = a.in + rhs * a.rhs_in;
+        T* p = a.p + rhs * a.rhs_in;
+        va[c] = ld16(r + i0);
+        vb[c] = ld16(r + i0 + N);
+        if (!first) {
+          va[c] += beta * ld16(p + i0);
+          vb[c] += beta * ld16(p + i0 + N);
+        }
+        st16(p + i0, va[c]);
+        st16(p + i0 + N, vb[c]);
+      } else {
+        if constexpr (sizeof(T) == 8) {
+          const long long* g = a.gin + rhs * a.rhs_in;
+          const double u = a.unit;
+          va[c] = R{(double)g[i0] * u, (double)g[i0 + 1] * u};
+          vb[c] = R{(double)g[i0 + N] * u, (double)g[i0 + N + 1] * u};
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < PER; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (ITEMS % NT == 0 || q < ITEMS) {
+      const int b = q / (N / RW), z = (q - b * (N / RW)) * RW;
+#pragma unroll
+      for (int j = 0; j < RW; ++j) lds[b * N + z + j] = V{va[c][j], vb[c][j]};
+    }
+  }
+  __syncthreads();
+  fft_tile<T, N, NB, NT, false, -1>(lds, a.tw);
+
+  // split the two real rows: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
+  V* om = a.out_main + rhs * a.rhs_main;
+  const int nk = a.nkz_out;
+  constexpr int ITEMS2 = NB * H / CW;
+  constexpr int PER2 = (ITEMS2 + NT - 1) / NT;
+#pragma unroll
+  for (int c = 0; c < PER2; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (!(ITEMS2 % NT == 0 || q < ITEMS2)) continue;
+    const int b = q / (H / CW), k0 = (q - b * (H / CW)) * CW;
+    if (k0 >= nk) continue;
+    R oa, ob;
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      const int k = k0 + j;
+      const V zk = lds[b * N + k];
+      const V zn = lds[b * N + ((N - k) % N)];
+      oa[2 * j] = T(0.5) * (zk.x + zn.x);
+      oa[2 * j + 1] = T(0.5) * (zk.y - zn.y);
+      ob[2 * j] = T(0.5) * (zk.y + zn.y);
+      ob[2 * j + 1] = T(-0.5) * (zk.x - zn.x);
+    }
+    const int64_t r0 = row0 + 2 * b;
+    st16(reinterpret_cast<T*>(om + r0 * nk + k0), oa);
+    st16(reinterpret_cast<T*>(om + (r0 + 1) * nk + k0), ob);
+  }
+  if (a.out_nyq) {
+    V* on = a.out_nyq + rhs * a.rhs_nyq;
+    for (int b = threadIdx.x; b < NB; b += NT) {
+      const V zh = lds[b * N + H];
+      const int64_t r0 = row0 + 2 * b;
+      on[r0] = V{zh.x, T(0)};
+      on[r0 + 1] = V{zh.y, T(0)};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z inverse: half spectrum -> real rows (+ fused CG / residual work)
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
+  using V = cplx<T>;
+  using R = vec16<T>;
+  constexpr int RW = 16 / sizeof(T);
+  constexpr int CW = 16 / sizeof(V);
+  constexpr int NB = z_nb<T, N>();
+  constexpr int H = N / 2;
+  __shared__ __align__(16) V lds[NB * N];
+  __shared__ double red[NT / 64];
+  const int rhs = blockIdx.y;
+  CgState* st = a.st ? a.st + rhs : nullptr;
+  if (st && skip_rhs(st, a.skip)) return;
+  const int64_t row0 = (int64_t)blockIdx.x * NB * 2;
+  const V* im = a.in_main + rhs * a.rhs_main;
+  const V* inq = a.in_nyq + rhs * a.rhs_nyq;
+
+  // Z_k = A_k + i B_k for k <= N/2 and Z_{N-k} = conj A_k + i conj B_k: every
+  // spectrum value is read once and written to both places.  Only the real
+  // parts of the k = 0 and k = N/2 entries enter (as in a real inverse DFT).
+  constexpr int ITEMS = NB * H / CW;
+  constexpr int PER = (ITEMS + NT - 1) / NT;
+  R va[PER], vb[PER];
+#pragma unroll
+  for (int c = 0; c < PER; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (ITEMS % NT == 0 || q < ITEMS) {
+      const int b = q / (H / CW), k0 = (q - b * (H / CW)) * CW;
+      const int64_t r0 = row0 + 2 * b;
+      va[c] = ld16(reinterpret_cast<const T*>(im + r0 * H + k0));
+      vb[c] = ld16(reinterpret_cast<const T*>(im + (r0 + 1) * H + k0));
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < PER; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (ITEMS % NT == 0 || q < ITEMS) {
+      const int b = q / (H / CW), k0 = (q - b * (H / CW)) * CW;
+#pragma unroll
+      for (int j = 0; j < CW; ++j) {
+        const int k = k0 + j;
+        const T ax = va[c][2 * j], ay = va[c][2 * j + 1];
+        const T bx = vb[c][2 * j], by = vb[c][2 * j + 1];
+        if (k == 0) {
+          lds[b * N] = V{ax, bx};
+        } else {
+          lds[b * N + k] = V{ax - by, ay + bx};
+          lds[b * N + N - k] = V{ax + by, bx - ay};
+        }
+      }
+    }
+  }
+  for (int b = threadIdx.x; b < NB; b += NT) {
+    const int64_t r0 = row0 + 2 * b;
+    lds[b * N + H] = V{inq[r0].x, inq[r0 + 1].x};
+  }
+  __syncthreads();
+  fft_tile<T, N, NB, NT, false, +1>(lds, a.tw);
+
+  constexpr int ITEMS3 = NB * N / RW;
+  constexpr int PER3 = (ITEMS3 + NT - 1) / NT;
+  double acc = 0.0;
+  T* out = a.out + rhs * a.rhs_out;
+  T nbar = T(0);
+  if constexpr (MODE != ZOUT_REAL) nbar = (T)st->nbar;
+#pragma unroll
+  for (int c = 0; c < PER3; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (!(ITEMS3 % NT == 0 || q < ITEMS3)) continue;
+    const int b = q / (N / RW), z = (q - b * (N / RW)) * RW;
+    const int64_t i0 = (row0 + 2 * b) * N + z, i1 = i0 + N;
+    R re, imv;
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const V v = lds[b * N + z + j];
+      re[j] = v.x;
+      imv[j] = v.y;
+    }
+    if constexpr (MODE == ZOUT_REAL) {
+      const T sc = (T)a.scale;
+      st16(out + i0, re * sc);
+      st16(out + i1, imv * sc);
+    } else if constexpr (MODE == ZOUT_CGQ || MODE == ZOUT_APPLY) {
+      const T* p = a.aux + rhs * a.rhs_aux;
+      const R p0 = ld16(p + i0), p1 = ld16(p + i1);
+      const R w0 = ld16(a.w + i0), w1 = ld16(a.w + i1);
+      const R q0 = re + (nbar * w0) * p0;
+      const R q1 = imv + (nbar * w1) * p1;
+      st16(out + i0, q0);
+      st16(out + i1, q1);
+      if constexpr (MODE == ZOUT_CGQ) {
+#pragma unroll
+        for (int j = 0; j < RW; ++j)
+          acc += (double)p0[j] * (double)q0[j] + (double)p1[j] * (double)q1[j];
+      }
+    } else if constexpr (sizeof(T) == 8) {  // ZOUT_RES: r = b - A x (FP64)
+      const T* x = a.aux + rhs * a.rhs_aux;
+      const double* bb = a.bvec + rhs * a.rhs_b;
+      const R x0 = ld16(x + i0), x1 = ld16(x + i1);
+      const R w0 = ld16(a.w + i0), w1 = ld16(a.w + i1);
+      const R r0 = ld16(bb + i0) - (re + (nbar * w0) * x0);
+      const R r1 = ld16(bb + i1) - (imv + (nbar * w1) * x1);
+      st16(out + i0, r0);
+      st16(out + i1, r1);
+#pragma unroll
+      for (int j = 0; j < RW; ++j) acc += r0[j] * r0[j] + r1[j] * r1[j];
+    }
+  }
+  if constexpr (MODE == ZOUT_CGQ || MODE == ZOUT_RES) {
+    const double part = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = part;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// strided passes (y or x axis)
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_strided(StrArgs<T> a) {
+  using V = cplx<T>;
+  using R = vec16<T>;
+  constexpr int TB = str_tb<T, N>();
+  constexpr int CW = 16 / sizeof(V);
+  constexpr bool VEC = (TB % CW) == 0;        // TB adjacent columns per row
+  constexpr int G = VEC ? CW : 1;             // complex values moved per access
+  constexpr int ITEMS = TB * N / G;
+  constexpr int PER = (ITEMS + NT - 1) / NT;
+  __shared__ __align__(16) V lds[TB * N];
+  const int rhs = blockIdx.y;
+  if (a.st && skip_rhs(a.st + rhs, a.skip)) return;
+  int blk = blockIdx.x;
+  const bool second = blk >= a.nblk0;
+  const Seg<T> s = second ? a.s1 : a.s0;
+  if (second) blk -= a.nblk0;
+  const int outer = blk / s.n_btiles;
+  const int b0 = (blk - outer * s.n_btiles) * TB;
+
+  const V* in = s.in + rhs * s.in_rhs + outer * s.in_outer + b0 * s.in_batch;
+  if (!s.axis_contig) {
+    // columns b are adjacent in memory (batch stride 1)
+    if constexpr (VEC) {
+      R buf[PER];
+#pragma unroll
+      for (int c = 0; c < PER; ++c) {
+        const int q = threadIdx.x + c * NT;
+        if (ITEMS % NT == 0 || q < ITEMS) {
+          const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+          buf[c] = ld16(reinterpret_cast<const T*>(in + i * s.in_axis + b));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < PER; ++c) {
+        const int q = threadIdx.x + c * NT;
+        if (ITEMS % NT == 0 || q < ITEMS) *reinterpret_cast<R*>(lds + q * CW) = buf[c];
+      }
+    } else {
+      for (int e = threadIdx.x; e < TB * N; e += NT) {
+        const int b = e % TB, i = e / TB;
+        lds[e] = in[i * s.in_axis + b];
+      }
+    }
+  } else {
+    // the FFT axis is contiguous (batch stride s.in_batch)
+    constexpr int AV = (N % CW == 0) ? CW : 1;
+    constexpr int IT = TB * N / AV;
+    constexpr int PA = (IT + NT - 1) / NT;
+    V buf[PA][AV];
+#pragma unroll
+    for (int c = 0; c < PA; ++c) {
+      const int q = threadIdx.x + c * NT;
+      if (IT % NT == 0 || q < IT) {
+        const int b = q / (N / AV), i = (q - b * (N / AV)) * AV;
+        if constexpr (AV == CW && CW > 1) {
+          const R v = ld16(reinterpret_cast<const T*>(in + b * s.in_batch + i));
+#pragma unroll
+          for (int j = 0; j < AV; ++j) buf[c][j] = V{v[2 * j], v[2 * j + 1]};
+        } else {
+          buf[c][0] = in[b * s.in_batch + i];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < PA; ++c) {
+      const int q = threadIdx.x + c * NT;
+      if (IT % NT == 0 || q < IT) {
+        const int b = q / (N / AV), i = (q - b * (N / AV)) * AV;
+#pragma unroll
+        for (int j = 0; j < AV; ++j) lds[(i + j) * TB + b] = buf[c][j];
+      }
+    }
+  }
+  __syncthreads();
+  if constexpr (MODE == SM_INV) fft_tile<T, N, TB, NT, true, +1>(lds, a.tw);
+  else fft_tile<T, N, TB, NT, true, -1>(lds, a.tw);
+
+  if constexpr (MODE == SM_FWD_LAM_INV) {
+    const int mo = s.lam_outer_signed ? signed_m(outer, N) : 0;
+    const int base = mo * mo + s.lam_const;
+    for (int e = threadIdx.x; e < TB * N; e += NT) {
+      const int b = e % TB, i = e / TB;
+      const int mi = signed_m(i, N);
+      const int mb = s.lam_batch_signed ? signed_m(b0 + b, N) : (b0 + b);
+      const T l = a.lam[base + mi * mi + mb * mb];
+      const V v = lds[e];
+      lds[e] = V{v.x * l, v.y * l};
+    }
+    __syncthreads();
+    fft_tile<T, N, TB, NT, true, +1>(lds, a.tw);
+  }
+
+  V* out = s.out + rhs * s.out_rhs + outer * s.out_outer + b0 * s.out_batch;
+  if constexpr (MODE == SM_FWD_CROP) {
+    const int no = s.n_out, h = no / 2;
+    for (int e = threadIdx.x; e < TB * no; e += NT) {
+      const int b = e % TB, o = e / TB;
+      V v = {T(0), T(0)};
+      if (o != h) v = lds[(o < h ? o : o + (N - no)) * TB + b];
+      out[o * s.out_axis + b] = v;
+    }
+  } else if (!s.axis_contig) {
+    if constexpr (VEC) {
+#pragma unroll
+      for (int c = 0; c < PER; ++c) {
+        const int q = threadIdx.x + c * NT;
+        if (ITEMS % NT == 0 || q < ITEMS) {
+          const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+          st16(reinterpret_cast<T*>(out + i * s.out_axis + b), *reinterpret_cast<const R*>(lds + q * CW));
+        }
+      }
+    } else {
+      for (int e = threadIdx.x; e < TB * N; e += NT) {
+        const int b = e % TB, i = e / TB;
+        out[i * s.out_axis + b] = lds[e];
+      }
+    }
+  } else {
+    constexpr int AV = (N % CW == 0) ? CW : 1;
+    constexpr int IT = TB * N / AV;
+    for (int q = threadIdx.x; q < IT; q += NT) {
+      const int b = q / (N / AV), i = (q - b * (N / AV)) * AV;
+      if constexpr (AV == CW && CW > 1) {
+        R v;
+#pragma unroll
+        for (int j = 0; j < AV; ++j) {
+          const V x = lds[(i + j) * TB + b];
+          v[2 * j] = x.x;
+          v[2 * j + 1] = x.y;
+        }
+        st16(reinterpret_cast<T*>(out + b * s.out_batch + i), v);
+      } else {
+        out[b * s.out_batch + i] = lds[i * TB + b];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finalize: sum the block partials of one reduction per RHS (fixed order)
+// and update the scalar CG state
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(256) void k_finalize(const double* partials, int nparts, int skip,
+                                                  CgState* st_all) {
+  __shared__ double red[4];
+  const int rhs = blockIdx.x;
+  CgState* st = st_all + rhs;
+  if (skip_rhs(st, skip)) return;
+  const double* p = partials + (int64_t)rhs * nparts;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 768 < nparts; i += 1024) {
+    s0 += p[i];
+    s1 += p[i + 256];
+    s2 += p[i + 512];
+    s3 += p[i + 768];
+  }
+  for (; i < nparts; i += 256) s0 += p[i];
+  const double tot = block_sum((s0 + s1) + (s2 + s3), red);
+  if (threadIdx.x != 0) return;
+  if constexpr (KIND == FIN_PQ) {
+    st->pq = tot;
+    if (!(tot > 0.0) || !isfinite(tot)) {
+      st->done = 1;
+      st->status = CG_BREAKDOWN;
+    } else {
+      st->alpha = st->rho / tot;
+    }
+  } else if constexpr (KIND == FIN_RR) {
+    const double rho_new = tot;
+    st->iter += 1;
+    const double rel = sqrt(rho_new) / st->bnorm;
+    st->rel = rel;
+    if (st->reliable) {
+      // the recursive residual decides when to refresh it in FP64; only the
+      // FP64 residual decides convergence
+      if (sqrt(rho_new) <= st->delta * st->rmax || rel <= st->tol || st->iter >= st->max_iter) {
+        st->done = 1;
+        st->status = CG_UPDATE;
+      }
+    } else if (rel <= st->tol) {
+      st->done = 1;
+      st->status = CG_CONVERGED;
+    } else if (st->iter >= st->max_iter) {
+      st->done = 1;
+      st->status = CG_MAXITER;
+    }
+    st->beta = rho_new / st->rho;
+    st->rho_old = st->rho;
+    st->rho = rho_new;
+    st->first = 0;
+  } else {  // FIN_RES
+    st->outer_rr = tot;
+  }
+}
+
+hipError_t launch_finalize(int kind, const double* partials, int nparts, int skip, CgState* st,
+                           int nrhs, hipStream_t s) {
+  switch (kind) {
+    case FIN_PQ:
+      hipLaunchKernelGGL(k_finalize<FIN_PQ>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      break;
+    case FIN_RR:
+      hipLaunchKernelGGL(k_finalize<FIN_RR>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      break;
+    case FIN_RES:
+      hipLaunchKernelGGL(k_finalize<FIN_RES>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// launchers (dispatch over the supported lengths)
+// ---------------------------------------------------------------------------
+#define WF_FOR_LENGTHS(X) \
+  X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+// FP32 kernels are only instantiated for target grids (<= 512).
+#define WF_FOR_F32(X) \
+  X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+
+bool fft_length_supported(int n, bool fp64) {
+  switch (n) {
+#define X(L) case L:
+    WF_FOR_LENGTHS(X)
+#undef X
+    return fp64 || n <= 512;
+    default: return false;
+  }
+}
+
+int strided_tb(int n, bool fp64) {
+  switch (n) {
+#define X(L) \
+  case L: return fp64 ? str_tb<double, L>() : str_tb<float, L>();
+    WF_FOR_LENGTHS(X)
+#undef X
+    default: return 0;
+  }
+}
+
+int zpass_nb(int n, bool fp64) {
+  switch (n) {
+#define X(L) \
+  case L: return fp64 ? z_nb<double, L>() : z_nb<float, L>();
+    WF_FOR_LENGTHS(X)
+#undef X
+    default: return 0;
+  }
+}
+
+int zpass_blocks(int n, int64_t nrows, bool fp64) { return (int)(nrows / (2 * zpass_nb(n, fp64))); }
+
+template <typename T, int N>
+static hipError_t zfwd_n(int mode, const ZfwdArgs<T>& a, int64_t nrows, int nrhs, hipStream_t s) {
+  constexpr int NB = z_nb<T, N>();
+  dim3 grid((unsigned)(nrows / (2 * NB)), (unsigned)nrhs);
+  switch (mode) {
+    case ZIN_REAL: hipLaunchKernelGGL((k_zfwd<T, N, ZIN_REAL>), grid, dim3(NT), 0, s, a); break;
+    case ZIN_CGP: hipLaunchKernelGGL((k_zfwd<T, N, ZIN_CGP>), grid, dim3(NT), 0, s, a); break;
+    case ZIN_I64:
+      if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((k_zfwd<T, N, ZIN_I64>), grid, dim3(NT), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t zinv_n(int mode, const ZinvArgs<T>& a, int64_t nrows, int nrhs, hipStream_t s) {
+  constexpr int NB = z_nb<T, N>();
+  dim3 grid((unsigned)(nrows / (2 * NB)), (unsigned)nrhs);
+  switch (mode) {
+    case ZOUT_REAL: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_REAL>), grid, dim3(NT), 0, s, a); break;
+    case ZOUT_CGQ: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_CGQ>), grid, dim3(NT), 0, s, a); break;
+    case ZOUT_RES:
+      if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((k_zinv<T, N, ZOUT_RES>), grid, dim3(NT), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
+    case ZOUT_APPLY: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_APPLY>), grid, dim3(NT), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t strided_n(int mode, const StrArgs<T>& a, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)(a.nblk0 + a.nblk1), (unsigned)nrhs);
+  switch (mode) {
+    case SM_FWD: hipLaunchKernelGGL((k_strided<T, N, SM_FWD>), grid, dim3(NT), 0, s, a); break;
+    case SM_INV: hipLaunchKernelGGL((k_strided<T, N, SM_INV>), grid, dim3(NT), 0, s, a); break;
+    case SM_FWD_LAM_INV:
+      hipLaunchKernelGGL((k_strided<T, N, SM_FWD_LAM_INV>), grid, dim3(NT), 0, s, a);
+      break;
+    case SM_FWD_CROP: hipLaunchKernelGGL((k_strided<T, N, SM_FWD_CROP>), grid, dim3(NT), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <> hipError_t launch_zfwd<double>(int n, int mode, const ZfwdArgs<double>& a, int64_t nrows,
+                                           int nrhs, hipStream_t s) {
+  switch (n) {
+#define X(L) \
+  case L: return zfwd_n<double, L>(mode, a, nrows, nrhs, s);
+    WF_FOR_LENGTHS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+template <> hipError_t launch_zfwd<float>(int n, int mode, const ZfwdArgs<float>& a, int64_t nrows,
+                                          int nrhs, hipStream_t s) {
+  switch (n) {
+#define X(L) \
+  case L: return zfwd_n<float, L>(mode, a, nrows, nrhs, s);
+    WF_FOR_F32(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+template <> hipError_t launch_zinv<double>(int n, int mode, const ZinvArgs<double>& a, int64_t nrows,
+                                           int nrhs, hipStream_t s) {
+  switch (n) {
+#define X(L) \
+  case L: return zinv_n<double, L>(mode, a, nrows, nrhs, s);
+    WF_FOR_F32(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+template <> hipError_t launch_zinv<float>(int n, int mode, const ZinvArgs<float>& a, int64_t nrows,
+                                          int nrhs, hipStream_t s) {
+  switch (n) {
+#define X(L) \
+  case L: return zinv_n<float, L>(mode, a, nrows, nrhs, s);
+    WF_FOR_F32(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+template <> hipError_t launch_strided<double>(int n, int mode, const StrArgs<double>& a, int nrhs,
+                                              hipStream_t s) {
+  switch (n) {
+#define X(L) \
+  case L: return strided_n<double, L>(mode, a, nrhs, s);
+    WF_FOR_LENGTHS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+template <> hipError_t launch_strided<float>(int n, int mode, const StrArgs<float>& a, int nrhs,
+                                             hipStream_t s) {
+  switch (n) {
+#define X(L) \
+  case L: return strided_n<float, L>(mode, a, nrhs, s);
+    WF_FOR_F32(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace wf

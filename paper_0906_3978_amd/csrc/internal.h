@@ -57,9 +57,37 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
-// Per-grid FFT resources for one precision.
-template <typename T> struct Spectral {
-  DevBuf tw;     // tw[m] = exp(-2 pi i m / n)
+// Live kernel timing: HIP events recorded around launches, harvested at
+// synchronisation points.
+struct Profiler {
+  bool on = false;
+  struct Pair {
+    hipEvent_t a, b;
+    int kind;
+    double bytes;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pair> pending;
+  int64_t launches[WF_PROF_KINDS] = {};
+  double ms[WF_PROF_KINDS] = {};
+  double bytes[WF_PROF_KINDS] = {};
+  ~Profiler();
+  void clear();
+  int begin(int kind, double bytes, hipStream_t s);
+  void end(int idx, hipStream_t s);
+  void harvest();   // all recorded events must have completed
+};
+
+// RAII bracket of one launch.
+struct ProfScope {
+  Profiler* p;
+  hipStream_t s;
+  int idx;
+  ProfScope(Profiler* p_, int kind, double bytes, hipStream_t s_)
+      : p(p_), s(s_), idx(p_ ? p_->begin(kind, bytes, s_) : -1) {}
+  ~ProfScope() {
+    if (p && idx >= 0) p->end(idx, s);
+  }
 };
 
 // Geometry of one n^3 grid and its half spectrum layout.
@@ -78,6 +106,7 @@ struct Grid {
 struct OperatorData {
   Grid g;
   DevBuf w64, w32, lam64, lam32, tw64, tw32;
+  Profiler* prof = nullptr;   // optional
 };
 
 // Workspace of solves on a grid for `nrhs` right-hand sides.
@@ -103,7 +132,7 @@ template <typename T>
 Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T* p,
                        cplx<T>* spec, int zout_mode, T* out, const T* aux,
                        const double* bvec, CgState* st, double* partials, int nrhs,
-                       bool check_done, hipStream_t s);
+                       int skip, hipStream_t s);
 
 // Forward transform only (test hook): z, y, x forward passes.
 template <typename T>

@@ -23,6 +23,7 @@ template <typename T> struct ZfwdArgs {
   int64_t rhs_in, rhs_main, rhs_nyq;  // per-RHS strides in elements
   const cplx<T>* tw;
   CgState* st;              // may be null
+  int32_t skip;             // SKIP_* (needs st)
 };
 
 template <typename T> struct ZinvArgs {
@@ -40,6 +41,7 @@ template <typename T> struct ZinvArgs {
   double* partials;         // per RHS: gridDim.x doubles
   const cplx<T>* tw;
   CgState* st;
+  int32_t skip;             // SKIP_*
 };
 
 // ---- strided passes (y or x axis), tiles of TB neighbouring pencils -------
@@ -59,11 +61,13 @@ template <typename T> struct StrArgs {
   int32_t nblk0, nblk1;
   const T* lam;
   const cplx<T>* tw;
-  const CgState* st;
+  const CgState* st;        // may be null
+  int32_t skip;             // SKIP_* (needs st)
 };
 
 int strided_tb(int n, bool fp64);   // batch width of a strided tile
 int zpass_nb(int n, bool fp64);     // pencils (row pairs) per z-pass block
+int zpass_blocks(int n, int64_t nrows, bool fp64);  // blocks of one z-pass launch
 bool fft_length_supported(int n, bool fp64);
 
 template <typename T> hipError_t launch_zfwd(int n, int mode, const ZfwdArgs<T>& a,
@@ -73,28 +77,37 @@ template <typename T> hipError_t launch_zinv(int n, int mode, const ZinvArgs<T>&
 template <typename T> hipError_t launch_strided(int n, int mode, const StrArgs<T>& a,
                                                 int nrhs, hipStream_t s);
 
+// Sums the block partials of one reduction (nparts per RHS, fixed order) and
+// updates the CG state: FIN_PQ -> alpha (or breakdown), FIN_RR -> iteration
+// bookkeeping, beta and stopping, FIN_RES -> outer_rr.
+enum FinKind : int { FIN_PQ = 0, FIN_RR = 1, FIN_RES = 2 };
+hipError_t launch_finalize(int kind, const double* partials, int nparts, int skip, CgState* st,
+                           int nrhs, hipStream_t s);
+
 // ---- vector kernels --------------------------------------------------------
 constexpr int VEC_THREADS = 256;
 int vec_blocks(int64_t m);
 
-// x = 0; r = (T)(src * (scaled ? st->scale : 1)); rho = r.r; bnorm; starts a CG solve
+// x = 0; r = (T) src; rho = r.r; bnorm; starts a CG solve
 template <typename T> hipError_t launch_cg_init(T* x, T* r, const double* src, int64_t m,
-                                                int64_t rhs_stride, int scaled, double* partials,
+                                                int64_t rhs_stride, double* partials,
                                                 CgState* st, int nrhs, hipStream_t s);
-// x += alpha p; r -= alpha q; rho' = r.r; convergence test; beta
+// x += alpha p; r -= alpha q; block partials of r.r (then FIN_RR)
 template <typename T> hipError_t launch_cg_update(T* x, T* r, const T* p, const T* q, int64_t m,
                                                   int64_t rhs_stride, double* partials,
                                                   CgState* st, int nrhs, hipStream_t s);
-// refinement: x64 += sqrt(outer_rr) * e32
-hipError_t launch_refine_add(double* x, const float* e, int64_t m, int64_t rhs_stride,
-                             const CgState* st, int nrhs, hipStream_t s);
-// r = b, x = 0, outer_rr = b.b, outer_bnorm
-hipError_t launch_outer_init(double* x, double* r, const double* b, int64_t m, int64_t rhs_stride,
-                             double* partials, CgState* st, int nrhs, hipStream_t s);
-// refinement: start the next inner solve (per-RHS outer test, budget, scale)
-hipError_t launch_inner_setup(CgState* st, double tol, int nrhs, hipStream_t s);
-// refinement: charge the inner iterations to the budget, note breakdowns
-hipError_t launch_inner_finish(CgState* st, int nrhs, hipStream_t s);
+// mixed precision with reliable updates:
+// start: x64 = 0, r64 = b, x32 = 0, r32 = (float) b; bnorm, rho, rmax
+hipError_t launch_rel_init(double* x64, double* r64, const double* b, float* x32, float* r32,
+                           int64_t m, int64_t rhs_stride, double* partials, CgState* st, int nrhs,
+                           hipStream_t s);
+// RHS waiting for an update: x64 += x32, x32 = 0
+hipError_t launch_rel_fold(double* x64, float* x32, int64_t m, int64_t rhs_stride,
+                           const CgState* st, int nrhs, hipStream_t s);
+// RHS waiting for an update (after r64 = b - A64 x64): r32 = (float) r64, rho,
+// convergence test on the FP64 residual, resume or stop
+hipError_t launch_rel_reset(float* r32, const double* r64, int64_t m, int64_t rhs_stride,
+                            double* partials, CgState* st, int nrhs, hipStream_t s);
 
 hipError_t launch_fill_i64(long long* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_c64(double2* p, int64_t n, hipStream_t s);

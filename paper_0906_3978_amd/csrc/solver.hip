@@ -1,11 +1,17 @@
 // Conjugate-gradient drivers for the Wiener system A s = b (eq:WF).
 //
 // FP64: plain CG from s = 0 (Hestenes-Stiefel), stopped on the recursive
-// relative residual.  MIXED: FP64 iterative refinement around FP32 CG --
-// r = b - A64 x (FP64 FFTs and diagonals), inner FP32 CG on r / ||r|| with
-// FP64 dot products down to inner_tol, x += ||r|| e -- stopped on the FP64
-// residual.  Both run several right-hand sides at once when asked: every
-// kernel launch covers all of them, each with its own scalars and stop flag.
+// relative residual.
+// MIXED: CG with an FP32 operator (FFTs and diagonals) and FP32 vectors, FP64
+// dot products, and FP64 "reliable updates" (Sleijpen & van der Vorst): each
+// time the recursive FP32 residual has dropped by `delta` since the last
+// update, the FP32 correction is folded into the FP64 solution, the residual
+// is recomputed as b - A x with the FP64 operator, and the iteration goes on
+// from that residual with the same search direction.  This is iterative
+// refinement that keeps the Krylov space (a restarted refinement would throw
+// it away at every step); convergence is decided on the FP64 residual only.
+// Both run several right-hand sides at once when asked: every kernel launch
+// covers all of them, each with its own scalars and stop flag.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -44,8 +50,13 @@ Status cg_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hi
   CgState* st = sw.state.as<CgState>();
   double* parts = sw.partials.as<double>();
   WF_TRY(operator_passes<T>(od, ZIN_CGP, v.r, v.p, v.spec, ZOUT_CGQ, v.q, v.p, nullptr, st, parts,
-                            nr, true, s));
-  WF_HIP(launch_cg_update<T>(v.x, v.r, v.p, v.q, od.g.m, od.g.m, parts, st, nr, s));
+                            nr, SKIP_DONE, s));
+  {
+    ProfScope ps(od.prof, sizeof(T) == 8 ? WF_PROF_UPDATE_F64 : WF_PROF_UPDATE_F32,
+                 6.0 * sizeof(T) * od.g.m * nr, s);
+    WF_HIP(launch_cg_update<T>(v.x, v.r, v.p, v.q, od.g.m, od.g.m, parts, st, nr, s));
+  }
+  WF_HIP(launch_finalize(FIN_RR, parts, vec_blocks(od.g.m), SKIP_DONE, st, nr, s));
   return {};
 }
 
@@ -59,6 +70,34 @@ Status iterate_until_done(const OperatorData& od, SolveWork& sw, Vecs<T> v, int 
     for (int i = 0; i < nr; ++i) all = all && sw.st_host[i].done;
     if (all) return {};
     for (int k = 0; k < check; ++k) WF_TRY(cg_iteration<T>(od, sw, v, nr, s));
+  }
+}
+
+// Mixed precision: FP32 iterations until every RHS has stopped; reliable
+// updates for the RHS that ask for one.
+Status iterate_reliable(const OperatorData& od, SolveWork& sw, int nr, int check, hipStream_t s) {
+  Vecs<float> v = v32(sw);
+  CgState* st = sw.state.as<CgState>();
+  double* parts = sw.partials.as<double>();
+  const Grid& g = od.g;
+  for (;;) {
+    WF_TRY(sw.pull_state(s));
+    bool all = true, update = false;
+    for (int i = 0; i < nr; ++i) {
+      all = all && sw.st_host[i].done;
+      update = update || sw.st_host[i].status == CG_UPDATE;
+    }
+    if (update) {
+      WF_HIP(launch_rel_fold(sw.x64.as<double>(), v.x, g.m, g.m, st, nr, s));
+      WF_TRY(operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr,
+                                     sw.spec64.as<double2>(), ZOUT_RES, sw.r64.as<double>(),
+                                     sw.x64.as<double>(), sw.b64.as<double>(), st, parts, nr,
+                                     SKIP_UNLESS_UPDATE, s));
+      WF_HIP(launch_rel_reset(v.r, sw.r64.as<double>(), g.m, g.m, parts, st, nr, s));
+      continue;
+    }
+    if (all) return {};
+    for (int k = 0; k < check; ++k) WF_TRY(cg_iteration<float>(od, sw, v, nr, s));
   }
 }
 
@@ -113,7 +152,7 @@ Status true_residual(const OperatorData& od, SolveWork& sw, double* out, int nr,
   return operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr,
                                  sw.spec64.as<double2>(), ZOUT_RES, out, sw.x64.as<double>(),
                                  sw.b64.as<double>(), sw.state.as<CgState>(),
-                                 sw.partials.as<double>(), nr, false, s);
+                                 sw.partials.as<double>(), nr, SKIP_NONE, s);
 }
 
 }  // namespace
@@ -144,7 +183,7 @@ Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
     WF_TRY(push_states(sw, st, s));
     tm.start(s);
     Vecs<double> v = v64(sw);
-    WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), g.m, g.m, 0,
+    WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), g.m, g.m,
                                   sw.partials.as<double>(), sw.state.as<CgState>(), nr, s));
     WF_TRY(iterate_until_done<double>(od, sw, v, nr, check, s));
     WF_TRY(true_residual(od, sw, v.q, nr, s));
@@ -169,70 +208,36 @@ Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
     return worst;
   }
 
-  // ---- mixed precision: FP64 refinement around FP32 CG -------------------
-  const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
-  const int max_outer = o.max_outer > 0 ? o.max_outer : 16;
+  // ---- mixed precision: FP32 CG with FP64 reliable updates -------------
   for (auto& e : st) {
-    e.outer_tol = o.tol;
-    e.budget = o.max_iter;
+    e.tol = o.tol;
+    e.max_iter = o.max_iter;
+    e.delta = o.inner_tol > 0 ? o.inner_tol : 0.1;
+    e.max_updates = o.max_outer;
   }
   WF_TRY(push_states(sw, st, s));
   tm.start(s);
   CgState* dst = sw.state.as<CgState>();
-  double* parts = sw.partials.as<double>();
-  WF_HIP(launch_outer_init(sw.x64.as<double>(), sw.r64.as<double>(), sw.b64.as<double>(), g.m, g.m,
-                           parts, dst, nr, s));
-  std::vector<std::vector<double>> hist(nr);
-  int outer = 0;
-  for (;; ++outer) {
-    WF_TRY(sw.pull_state(s));
-    bool any = false;
-    for (int i = 0; i < nr; ++i) {
-      CgState& c = sw.st_host[i];
-      if (c.outer_status != CG_RUNNING) continue;
-      const double rel = c.outer_bnorm > 0 ? std::sqrt(c.outer_rr) / c.outer_bnorm : 0.0;
-      hist[i].push_back(rel);
-      const size_t k = hist[i].size();
-      if (rel <= o.tol || c.budget <= 0) continue;
-      if (k >= 3 && rel > 0.5 * hist[i][k - 3]) {
-        // refinement stagnates: stop this RHS (the caller may rerun in FP64)
-        const int32_t stop = CG_STOPPED;
-        WF_HIP(hipMemcpyAsync(reinterpret_cast<char*>(dst + i) + offsetof(CgState, outer_status),
-                              &stop, sizeof stop, hipMemcpyHostToDevice, s));
-        WF_HIP(hipStreamSynchronize(s));
-        c.outer_status = CG_STOPPED;
-        continue;
-      }
-      any = true;
-    }
-    if (!any || outer >= max_outer) break;
-    Vecs<float> v = v32(sw);
-    WF_HIP(launch_inner_setup(dst, inner_tol, nr, s));
-    WF_HIP(launch_cg_init<float>(v.x, v.r, sw.r64.as<double>(), g.m, g.m, 1, parts, dst, nr, s));
-    WF_TRY(iterate_until_done<float>(od, sw, v, nr, check, s));
-    WF_HIP(launch_inner_finish(dst, nr, s));
-    WF_HIP(launch_refine_add(sw.x64.as<double>(), v.x, g.m, g.m, dst, nr, s));
-    WF_TRY(true_residual(od, sw, sw.r64.as<double>(), nr, s));
-  }
+  WF_HIP(launch_rel_init(sw.x64.as<double>(), sw.r64.as<double>(), sw.b64.as<double>(),
+                         sw.x32.as<float>(), sw.r32.as<float>(), g.m, g.m,
+                         sw.partials.as<double>(), dst, nr, s));
+  WF_TRY(iterate_reliable(od, sw, nr, check, s));
   const double ms = tm.stop(s);
   WF_TRY(sw.pull_state(s));
   for (int i = 0; i < nr; ++i) {
     const CgState& c = sw.st_host[i];
     wf_solve_info& in = infos[i];
     in = wf_solve_info{};
-    in.iters_total = o.max_iter - c.budget;
-    in.outer_steps = c.outer_steps;
+    in.iters_total = c.iter;
+    in.outer_steps = c.updates;
     in.rel_res_recursive = c.rel;
-    const double rel = c.outer_bnorm > 0 ? std::sqrt(c.outer_rr) / c.outer_bnorm : 0.0;
-    in.rel_res_true = rel;
+    in.rel_res_true = c.bnorm > 0 ? std::sqrt(c.outer_rr) / c.bnorm : 0.0;
     in.time_ms = ms;
-    in.model_bytes = (in.iters_total * model_bytes_iteration(false) +
-                      c.outer_steps * (model_bytes_residual() + 36.0) + 24.0) * M;
+    // FP32 iterations; per update: fold (x64 rw, x32 rw), FP64 residual, reset (r64 r, r32 w)
+    in.model_bytes = (c.iter * model_bytes_iteration(false) +
+                      c.updates * (model_bytes_residual() + 24.0 + 12.0) + 40.0) * M;
     in.nbar = c.nbar;
-    wf_status stt;
-    if (c.outer_status == CG_BREAKDOWN) stt = WF_EBREAKDOWN;
-    else if (rel <= o.tol) stt = WF_OK;
-    else stt = WF_ENOTCONV;
+    const wf_status stt = map_cg_status(c.status);
     in.status = stt;
     if (severity(stt) > severity(worst.code))
       worst = fail(stt, std::string("rhs ") + std::to_string(i) + ": " + wf_status_str(stt));
@@ -252,7 +257,7 @@ Status fp64_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, do
   st[0].max_iter = o.max_iter;
   WF_TRY(push_states(sw, st, s));
   Vecs<double> v = v64(sw);
-  WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), od.g.m, od.g.m, 0,
+  WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), od.g.m, od.g.m,
                                 sw.partials.as<double>(), sw.state.as<CgState>(), 1, s));
   return {};
 }

@@ -167,14 +167,18 @@ def random_axis(rng):
 
 def gaussian_field(ptab, n, box, seed):
     """Gaussian random field with spectrum P (per-cell units P/dV), zero mean
-    mode, built by colouring white noise in Fourier space."""
+    mode, built by colouring white noise in Fourier space.  Uses scipy's FFT on
+    all host cores (its result does not depend on the thread count)."""
+    import scipy.fft as sf
     rng = np.random.Generator(np.random.PCG64(seed))
     eps = rng.standard_normal((n, n, n))
     dv = (box / n) ** 3
     amp = np.sqrt(ptab[_m2_grid(n)] / dv)
     amp[0, 0, 0] = 0.0
-    g = np.fft.irfftn(np.fft.rfftn(eps) * amp, s=(n, n, n), axes=(0, 1, 2))
-    return g
+    ek = sf.rfftn(eps, workers=-1)
+    del eps
+    ek *= amp
+    return sf.irfftn(ek, s=(n, n, n), axes=(0, 1, 2), workers=-1)
 
 
 def lognormal_density(ptab, n, box, seed):

@@ -107,7 +107,7 @@ def test_converged_solve_fp64(ctx, pl32):
 
 def test_mixed_solve_error(ctx, pl32):
     _load(ctx, pl32)
-    x, info = ctx.solve(precision="mixed", tol=1e-10, max_iter=20000, inner_tol=1e-5)
+    x, info = ctx.solve(precision="mixed", tol=1e-10, max_iter=20000)
     assert info.status == WF_OK
     assert info.outer_steps >= 2
     assert info.rel_res_true <= 1e-10
