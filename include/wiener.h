@@ -281,8 +281,11 @@ wf_status wf_server_submit(wf_server* srv, const wf_request* req,
 /* done = 1 once the result is ready (info filled, may be NULL). */
 wf_status wf_server_poll(wf_server* srv, uint64_t ticket, int32_t* done,
                          wf_solve_info* info);
-/* Copies the result (n^3 doubles, host) and releases the ticket. */
+/* Copies the result (n^3 doubles, host) and releases the ticket.  A failed
+ * request returns its error (a cancelled one WF_ESTATE) and writes nothing. */
 wf_status wf_server_fetch(wf_server* srv, uint64_t ticket, double* s_out);
+/* Stops a queued or running request at its next chunk boundary; poll then
+ * reports it done with status WF_ESTATE. */
 wf_status wf_server_cancel(wf_server* srv, uint64_t ticket);
 wf_status wf_server_stats_get(wf_server* srv, wf_server_stats* stats);
 const char* wf_server_last_error(const wf_server* srv);

@@ -6,5 +6,5 @@ supersampling, and solves the signal-space Wiener filter of Kitaura et al.
 (eq:WF, Sec. 3.3.1) by conjugate gradients in FP64 or mixed precision.  This
 package is its ctypes binding; see ``Context``.
 """
-from ._lib import (Context, Info, WienerError, footprint_bytes, lib, opts,  # noqa: F401
+from ._lib import (Context, Info, Server, WienerError, footprint_bytes, lib, opts,  # noqa: F401
                    SCHEMES, PRECISIONS, STATUS_NAMES, LIB_PATH, SIGNATURES)

@@ -373,3 +373,94 @@ def _numel(a):
     if isinstance(a, np.ndarray):
         return a.size
     return a.numel()
+
+
+class Server:
+    """Continuous-batching reconstruction server (wf_server_*).  Device memory
+    for the whole budget is taken once (torch's caching allocator by default);
+    requests are admitted into it as they fit."""
+
+    def __init__(self, device=0, hbm_budget=8 << 30, max_active=8, torch_allocator=True):
+        L = lib()
+        self._L = L
+        self._cbs = (ALLOC_FN(), FREE_FN())
+        if torch_allocator:
+            import torch
+            torch.cuda.set_device(device)
+            self._cbs = _torch_allocator(device)
+        h = C.c_void_p()
+        code = L.wf_server_create(C.byref(h), device, int(hbm_budget), int(max_active),
+                                  self._cbs[0], self._cbs[1], None)
+        if code != WF_OK:
+            raise WienerError(code, L.wf_status_str(code).decode())
+        self._h = h
+
+    def _err(self, code):
+        msg = self._L.wf_server_last_error(self._h)
+        raise WienerError(code, msg.decode() if msg else "")
+
+    def submit(self, n, box, w, p_by_m2, xyz, scheme="cic", supersample=2, **kw):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        p = np.ascontiguousarray(p_by_m2, dtype=np.float64)
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        req = Request(int(n), float(box), w.ctypes.data, p.ctypes.data,
+                      xyz.ctypes.data if len(xyz) else None, len(xyz), SCHEMES[scheme],
+                      int(supersample), opts(**kw))
+        t = C.c_uint64()
+        code = self._L.wf_server_submit(self._h, C.byref(req), C.byref(t))
+        if code != WF_OK:
+            self._err(code)
+        return int(t.value)
+
+    def poll(self, ticket):
+        d = C.c_int32()
+        si = SolveInfo()
+        code = self._L.wf_server_poll(self._h, ticket, C.byref(d), C.byref(si))
+        if code != WF_OK:
+            self._err(code)
+        return bool(d.value), (_info(si) if d.value else None)
+
+    def fetch(self, ticket, n, allow=(WF_OK,)):
+        out = np.empty((n, n, n), dtype=np.float64)
+        code = self._L.wf_server_fetch(self._h, ticket, out.ctypes.data)
+        if code not in allow:
+            self._err(code)
+        return out
+
+    def wait(self, ticket, n, timeout=120.0, allow=(WF_OK,)):
+        import time
+        t0 = time.time()
+        while True:
+            done, info = self.poll(ticket)
+            if done:
+                return self.fetch(ticket, n, allow), info
+            if time.time() - t0 > timeout:
+                raise TimeoutError(f"request {ticket} not done after {timeout} s")
+            time.sleep(0.0005)
+
+    def cancel(self, ticket):
+        code = self._L.wf_server_cancel(self._h, ticket)
+        if code != WF_OK:
+            self._err(code)
+
+    def stats(self):
+        st = ServerStats()
+        self._L.wf_server_stats_get(self._h, C.byref(st))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.wf_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

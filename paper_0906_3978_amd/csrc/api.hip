@@ -134,7 +134,7 @@ wf_status wf_set_grid(wf_ctx* c, int32_t n, double box) {
     c->have_grid = c->have_mask = c->have_power = c->have_gal = c->have_rhs = false;
     c->solve_active = false;
     c->dep_scheme = -1;
-    s = make_twiddles(c->al, n, c->od.tw64, &c->od.tw32);
+    s = make_twiddles(c->al, n, c->od.tw64, &c->od.tw32, c->stream);
   }
   if (s.ok()) c->have_grid = true;
   return finish(c, s);

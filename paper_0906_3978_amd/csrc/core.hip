@@ -146,7 +146,7 @@ Status SolveWork::pull_state(hipStream_t s) {
   return {};
 }
 
-Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32) {
+Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32, hipStream_t st) {
   std::vector<double> t(2 * (size_t)n);
   std::vector<float> f(2 * (size_t)n);
   const double two_pi = 6.283185307179586476925286766559;
@@ -164,11 +164,12 @@ Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32) {
     f[2 * m + 1] = (float)s;
   }
   WF_TRY(tw64.ensure(al, t.size() * 8));
-  WF_HIP(hipMemcpy(tw64.p, t.data(), t.size() * 8, hipMemcpyHostToDevice));
+  WF_HIP(hipMemcpyAsync(tw64.p, t.data(), t.size() * 8, hipMemcpyHostToDevice, st));
   if (tw32) {
     WF_TRY(tw32->ensure(al, f.size() * 4));
-    WF_HIP(hipMemcpy(tw32->p, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    WF_HIP(hipMemcpyAsync(tw32->p, f.data(), f.size() * 4, hipMemcpyHostToDevice, st));
   }
+  WF_HIP(hipStreamSynchronize(st));  // the host tables go out of scope
   return {};
 }
 
@@ -405,7 +406,7 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
                 8.0 * mf + 2 * 16.0 * nf * nf * h + 2 * 16.0 * nf * n * h + 16.0 * g.spec_total * 5 +
                     8.0 * g.m,
                 s);
-  if (dw.tw_fine.bytes < (size_t)nf * 16) WF_TRY(make_twiddles(al, nf, dw.tw_fine, nullptr));
+  if (dw.tw_fine.bytes < (size_t)nf * 16) WF_TRY(make_twiddles(al, nf, dw.tw_fine, nullptr, s));
   const int64_t fine_spec = (int64_t)nf * nf * h;
   WF_TRY(dw.fine_spec.ensure(al, (size_t)fine_spec * 16));
   auto* fs = dw.fine_spec.as<double2>();

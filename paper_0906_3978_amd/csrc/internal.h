@@ -123,7 +123,7 @@ struct SolveWork {
   Status pull_state(hipStream_t s);
 };
 
-Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32);
+Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32, hipStream_t s);
 Status upload(void* dst, const void* src, size_t bytes, wf_mem mem, hipStream_t s);
 Status download(void* dst, const void* src, size_t bytes, wf_mem mem, hipStream_t s);
 

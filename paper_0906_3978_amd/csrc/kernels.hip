@@ -258,6 +258,28 @@ hipError_t launch_rel_reset(float* r32, const double* r64, int64_t m, int64_t rs
   return hipGetLastError();
 }
 
+// Initialises the scalar state of a solve whose nbar was written to the device
+// by the data-vector kernel (used by the server, which never waits on it).
+__global__ void k_state_init(CgState* st_all, const double* nbar, double tol, int32_t max_iter,
+                             double delta, int32_t max_updates) {
+  if (threadIdx.x != 0) return;
+  CgState* st = st_all + blockIdx.x;
+  CgState z{};
+  z.nbar = nbar[blockIdx.x];
+  z.tol = tol;
+  z.max_iter = max_iter;
+  z.delta = delta;
+  z.max_updates = max_updates;
+  *st = z;
+}
+
+hipError_t launch_state_init(CgState* st, const double* nbar, double tol, int32_t max_iter,
+                             double delta, int32_t max_updates, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(nrhs), dim3(64), 0, s, st, nbar, tol, max_iter, delta,
+                     max_updates);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // fills and conversions
 // ---------------------------------------------------------------------------

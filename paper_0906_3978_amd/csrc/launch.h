@@ -109,6 +109,10 @@ hipError_t launch_rel_fold(double* x64, float* x32, int64_t m, int64_t rhs_strid
 hipError_t launch_rel_reset(float* r32, const double* r64, int64_t m, int64_t rhs_stride,
                             double* partials, CgState* st, int nrhs, hipStream_t s);
 
+// state of nrhs solves from device-resident nbar values
+hipError_t launch_state_init(CgState* st, const double* nbar, double tol, int32_t max_iter,
+                             double delta, int32_t max_updates, int nrhs, hipStream_t s);
+
 hipError_t launch_fill_i64(long long* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_c64(double2* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s);

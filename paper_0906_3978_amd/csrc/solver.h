@@ -22,6 +22,18 @@ struct SolveRequest {
 // Returns the worst status; infos[i] per RHS.
 Status run_solve(const SolveRequest& rq, wf_solve_info* infos);
 
+// Asynchronous building blocks (no host synchronisation): the CG states
+// must already hold tol, max_iter, delta, max_updates and nbar.
+Status solve_start(const OperatorData& od, SolveWork& sw, int nr, bool mixed, hipStream_t s);
+Status solve_chunk(const OperatorData& od, SolveWork& sw, int nr, bool mixed, int iters,
+                   hipStream_t s);
+// mixed: reliable update of the RHS whose state asks for one
+Status solve_update(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s);
+// FP64: ||b - A x||^2 into outer_rr
+Status solve_true_residual(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s);
+void solve_infos(const CgState* st, int nr, bool mixed, const Grid& g, double ms,
+                 wf_solve_info* infos);
+
 // Stepwise FP64 solve of one RHS (checkpoint / resume).
 Status fp64_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, double nbar,
                   const wf_solve_opts& o, hipStream_t s);

@@ -157,6 +157,69 @@ Status true_residual(const OperatorData& od, SolveWork& sw, double* out, int nr,
 
 }  // namespace
 
+Status solve_start(const OperatorData& od, SolveWork& sw, int nr, bool mixed, hipStream_t s) {
+  const Grid& g = od.g;
+  if (mixed) {
+    WF_HIP(launch_rel_init(sw.x64.as<double>(), sw.r64.as<double>(), sw.b64.as<double>(),
+                           sw.x32.as<float>(), sw.r32.as<float>(), g.m, g.m,
+                           sw.partials.as<double>(), sw.state.as<CgState>(), nr, s));
+  } else {
+    Vecs<double> v = v64(sw);
+    WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), g.m, g.m,
+                                  sw.partials.as<double>(), sw.state.as<CgState>(), nr, s));
+  }
+  return {};
+}
+
+Status solve_chunk(const OperatorData& od, SolveWork& sw, int nr, bool mixed, int iters,
+                   hipStream_t s) {
+  if (mixed) {
+    Vecs<float> v = v32(sw);
+    for (int k = 0; k < iters; ++k) WF_TRY(cg_iteration<float>(od, sw, v, nr, s));
+  } else {
+    Vecs<double> v = v64(sw);
+    for (int k = 0; k < iters; ++k) WF_TRY(cg_iteration<double>(od, sw, v, nr, s));
+  }
+  return {};
+}
+
+Status solve_update(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s) {
+  const Grid& g = od.g;
+  CgState* st = sw.state.as<CgState>();
+  double* parts = sw.partials.as<double>();
+  WF_HIP(launch_rel_fold(sw.x64.as<double>(), sw.x32.as<float>(), g.m, g.m, st, nr, s));
+  WF_TRY(operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr, sw.spec64.as<double2>(),
+                                 ZOUT_RES, sw.r64.as<double>(), sw.x64.as<double>(),
+                                 sw.b64.as<double>(), st, parts, nr, SKIP_UNLESS_UPDATE, s));
+  WF_HIP(launch_rel_reset(sw.r32.as<float>(), sw.r64.as<double>(), g.m, g.m, parts, st, nr, s));
+  return {};
+}
+
+Status solve_true_residual(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s) {
+  return true_residual(od, sw, sw.q64.as<double>(), nr, s);
+}
+
+void solve_infos(const CgState* st, int nr, bool mixed, const Grid& g, double ms,
+                 wf_solve_info* infos) {
+  const double M = (double)g.m;
+  for (int i = 0; i < nr; ++i) {
+    const CgState& c = st[i];
+    wf_solve_info& in = infos[i];
+    in = wf_solve_info{};
+    in.iters_total = c.iter;
+    in.outer_steps = mixed ? c.updates : 0;
+    in.rel_res_recursive = c.bnorm > 0 ? c.rel : 0.0;
+    in.rel_res_true = c.bnorm > 0 ? std::sqrt(c.outer_rr) / c.bnorm : 0.0;
+    in.time_ms = ms;
+    // mixed: FP32 iterations; per update: fold (x64 rw, x32 rw), FP64 residual, reset
+    in.model_bytes = mixed ? (c.iter * model_bytes_iteration(false) +
+                              c.updates * (model_bytes_residual() + 24.0 + 12.0) + 40.0) * M
+                           : (c.iter * model_bytes_iteration(true) + model_bytes_residual()) * M;
+    in.nbar = c.nbar;
+    in.status = map_cg_status(c.status);
+  }
+}
+
 Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
   const OperatorData& od = *rq.od;
   const Grid& g = od.g;
@@ -171,74 +234,27 @@ Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
   for (int i = 0; i < nr; ++i) {
     st[i] = CgState{};
     st[i].nbar = rq.nbar[i];
-  }
-  Timer tm;
-  const double M = (double)g.m;
-  Status worst{};
-  if (!mixed) {
-    for (auto& e : st) {
-      e.tol = o.tol;
-      e.max_iter = o.max_iter;
-    }
-    WF_TRY(push_states(sw, st, s));
-    tm.start(s);
-    Vecs<double> v = v64(sw);
-    WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), g.m, g.m,
-                                  sw.partials.as<double>(), sw.state.as<CgState>(), nr, s));
-    WF_TRY(iterate_until_done<double>(od, sw, v, nr, check, s));
-    WF_TRY(true_residual(od, sw, v.q, nr, s));
-    const double ms = tm.stop(s);
-    WF_TRY(sw.pull_state(s));
-    for (int i = 0; i < nr; ++i) {
-      const CgState& c = sw.st_host[i];
-      wf_solve_info& in = infos[i];
-      in = wf_solve_info{};
-      in.iters_total = c.iter;
-      in.outer_steps = 0;
-      in.rel_res_recursive = c.bnorm > 0 ? c.rel : 0.0;
-      in.rel_res_true = c.bnorm > 0 ? std::sqrt(c.outer_rr) / c.bnorm : 0.0;
-      in.time_ms = ms;
-      in.model_bytes = (c.iter * model_bytes_iteration(true) + model_bytes_residual()) * M;
-      in.nbar = c.nbar;
-      in.status = map_cg_status(c.status);
-      if (severity((wf_status)in.status) > severity(worst.code))
-        worst = fail((wf_status)in.status, std::string("rhs ") + std::to_string(i) + ": " +
-                                               wf_status_str((wf_status)in.status));
-    }
-    return worst;
-  }
-
-  // ---- mixed precision: FP32 CG with FP64 reliable updates -------------
-  for (auto& e : st) {
-    e.tol = o.tol;
-    e.max_iter = o.max_iter;
-    e.delta = o.inner_tol > 0 ? o.inner_tol : 0.1;
-    e.max_updates = o.max_outer;
+    st[i].tol = o.tol;
+    st[i].max_iter = o.max_iter;
+    st[i].delta = o.inner_tol > 0 ? o.inner_tol : 0.1;
+    st[i].max_updates = o.max_outer;
   }
   WF_TRY(push_states(sw, st, s));
+  Timer tm;
   tm.start(s);
-  CgState* dst = sw.state.as<CgState>();
-  WF_HIP(launch_rel_init(sw.x64.as<double>(), sw.r64.as<double>(), sw.b64.as<double>(),
-                         sw.x32.as<float>(), sw.r32.as<float>(), g.m, g.m,
-                         sw.partials.as<double>(), dst, nr, s));
-  WF_TRY(iterate_reliable(od, sw, nr, check, s));
+  WF_TRY(solve_start(od, sw, nr, mixed, s));
+  if (mixed) {
+    WF_TRY(iterate_reliable(od, sw, nr, check, s));
+  } else {
+    WF_TRY(iterate_until_done<double>(od, sw, v64(sw), nr, check, s));
+    WF_TRY(solve_true_residual(od, sw, nr, s));
+  }
   const double ms = tm.stop(s);
   WF_TRY(sw.pull_state(s));
+  solve_infos(sw.st_host, nr, mixed, g, ms, infos);
+  Status worst{};
   for (int i = 0; i < nr; ++i) {
-    const CgState& c = sw.st_host[i];
-    wf_solve_info& in = infos[i];
-    in = wf_solve_info{};
-    in.iters_total = c.iter;
-    in.outer_steps = c.updates;
-    in.rel_res_recursive = c.rel;
-    in.rel_res_true = c.bnorm > 0 ? std::sqrt(c.outer_rr) / c.bnorm : 0.0;
-    in.time_ms = ms;
-    // FP32 iterations; per update: fold (x64 rw, x32 rw), FP64 residual, reset (r64 r, r32 w)
-    in.model_bytes = (c.iter * model_bytes_iteration(false) +
-                      c.updates * (model_bytes_residual() + 24.0 + 12.0) + 40.0) * M;
-    in.nbar = c.nbar;
-    const wf_status stt = map_cg_status(c.status);
-    in.status = stt;
+    const wf_status stt = (wf_status)infos[i].status;
     if (severity(stt) > severity(worst.code))
       worst = fail(stt, std::string("rhs ") + std::to_string(i) + ": " + wf_status_str(stt));
   }
