@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 # against the FP64 oracle solution stays below 1e-6 (the error is a few
 # hundred times the residual on these problems).
 DEFAULT_TOL = 2e-9
-KERNEL_SOURCES = ["paper_0906_3978_amd/csrc/kernels.hip", "paper_0906_3978_amd/csrc/fft.h",
+KERNEL_SOURCES = ["paper_0906_3978_amd/csrc/fftpass.hip", "paper_0906_3978_amd/csrc/kernels.hip",
+                  "paper_0906_3978_amd/csrc/fft.h",
                   "paper_0906_3978_amd/csrc/common.h"]
 
 
@@ -82,6 +83,115 @@ def cpu_baseline(wl, ptab, w, n_gal, iters_fp64, sample_iters=3):
                        f"{iters_fp64} iterations of one FP64 solve; gridding not included")}
 
 
+def serve(n_req, tol, seed=5000):
+    """Serving stream: requests drawn by synth.serving_request (grids 64..384,
+    random caps, radial scales, spectrum amplitudes and catalogue sizes).
+    Phase A serves them one at a time (isolated capacity, and the reference
+    results); phase B replays them with Poisson arrivals at 0.7 x that
+    capacity through the continuous-batching server.  Every result of B must
+    equal its phase-A result bit for bit."""
+    import synth
+    import paper_0906_3978_amd as wf
+    t = time.perf_counter()
+    reqs = []
+    for i in range(n_req):
+        wl = synth.serving_request(i, base_seed=seed + 1)
+        ptab = wl.ptab()
+        w = wl.mask()
+        cat = wl.catalogue(ptab, w)
+        reqs.append((wl, w, ptab, cat.xyz))
+    log(f"[serve] generated {n_req} requests ({time.perf_counter() - t:.1f} s), grids "
+        f"{sorted(set(r[0].n for r in reqs))}")
+    budget = 96 << 30
+    kw = dict(precision="mixed", tol=tol, max_iter=100000)
+
+    def submit(srv, r):
+        wl, w, ptab, xyz = r
+        return srv.submit(wl.n, wl.box, w, ptab, xyz, wl.scheme, wl.supersample, **kw)
+
+    alone = []
+    with wf.Server(0, hbm_budget=budget, max_active=1) as srv:
+        t0 = time.perf_counter()
+        for r in reqs:
+            x, info = srv.wait(submit(srv, r), r[0].n, timeout=600)
+            alone.append((x, info))
+        t_alone = time.perf_counter() - t0
+    cap = n_req / t_alone
+    rate = 0.7 * cap
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    with wf.Server(0, hbm_budget=budget, max_active=8) as srv:
+        tickets = []
+        t0 = time.perf_counter()
+        next_t = 0.0
+        for r, g in zip(reqs, gaps):
+            next_t += g
+            while time.perf_counter() - t0 < next_t:
+                time.sleep(0.0002)
+            tickets.append(submit(srv, r))
+        outs = [srv.wait(tk, r[0].n, timeout=600) for tk, r in zip(tickets, reqs)]
+        st = srv.stats()
+    same = all(np.array_equal(a[0], b[0]) for a, b in zip(alone, outs))
+    worst = max(b[1].rel_res_true for b in outs)
+    res = {"requests": n_req, "grids": sorted(set(r[0].n for r in reqs)),
+           "isolated_solves_per_s": round(cap, 4), "arrival_rate_per_s": round(rate, 4),
+           "solves_per_s": round(st["solves_per_s"], 4), "p50_ms": round(st["p50_ms"], 2),
+           "p99_ms": round(st["p99_ms"], 2), "completed": st["completed"],
+           "failed": st["failed"], "peak_bytes": st["peak_bytes"],
+           "results_equal_alone_and_in_mix": bool(same), "worst_rel_res_true": worst}
+    log(f"[serve] {res}")
+    return res
+
+
+def batch_run(nrhs, tol):
+    """Multi-RHS batch: nrhs lognormal-Poisson catalogues of 1e6 galaxies on a
+    shared 256^3 / 500 Mpc grid, mask and BBKS prior, CIC 2x supersampled,
+    solved in one mixed-precision batch (every pass one launch for all RHS);
+    compared with the same catalogues solved one at a time."""
+    import synth
+    import torch
+    import paper_0906_3978_amd as wf
+    wl = synth.workload("bbks256")
+    ptab = wl.ptab()
+    w = wl.mask()
+    cats = []
+    t = time.perf_counter()
+    for j in range(nrhs):
+        wl.seed = 4000 + 3 * j
+        cats.append(wl.catalogue(ptab, w).xyz)
+    log(f"[batch] generated {nrhs} catalogues ({time.perf_counter() - t:.1f} s)")
+    ctx = wf.Context(0)
+    ctx.set_grid(wl.n, wl.box)
+    ctx.set_mask(w)
+    ctx.set_power(ptab)
+    kw = dict(precision="mixed", tol=tol, max_iter=100000)
+    ctx.solve_batch(cats[:2], "cic", 2, **kw)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    outs, infos = ctx.solve_batch(cats, "cic", 2, **kw)
+    t_batch = time.perf_counter() - t
+    t = time.perf_counter()
+    singles = []
+    for xyz in cats:
+        ctx.set_galaxies(xyz)
+        ctx.deposit("cic", 2)
+        x, _ = ctx.solve(**kw)
+        singles.append(x)
+    t_single = time.perf_counter() - t
+    same = all(np.array_equal(a, b) for a, b in zip(outs, singles))
+    iters = [i.iters_total for i in infos]
+    res = {"nrhs": nrhs, "n": wl.n, "batch_s": round(t_batch, 3),
+           "solves_per_s": round(nrhs / t_batch, 3), "sequential_s": round(t_single, 3),
+           "speedup_batch_over_sequential": round(t_single / t_batch, 3),
+           "iters_min_max": [min(iters), max(iters)],
+           "worst_rel_res_true": max(i.rel_res_true for i in infos),
+           "results_equal_single": bool(same),
+           "note": "host catalogues (PCIe copies inside both timings)"}
+    log(f"[batch] {res}")
+    ctx.close()
+    return res
+
+
 def traffic_for(kernel, launch_bytes):
     """HBM bytes per launch from committed rocprofv3 PMC counters, if they were
     taken on the current kernel sources."""
@@ -108,6 +218,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--profile-iters", type=int, default=0,
+                    help="profiling run: one deposit, this many mixed iterations and a 1 GiB "
+                         "device copy (the reference for scaling HBM counters), then exit")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="also run a serving stream of this many requests")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also run the multi-RHS batch: this many 256^3 catalogues in one solve")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -133,6 +250,19 @@ def main():
     torch.cuda.synchronize()
 
     solve_kw = dict(precision="mixed", tol=args.tol, max_iter=100000, inner_tol=args.inner_tol)
+
+    if args.profile_iters:
+        ctx.set_galaxies(xyz_d)
+        ctx.deposit(wl.scheme, wl.supersample)
+        _, info = ctx.solve(out=out, precision="mixed", tol=0.0, max_iter=args.profile_iters,
+                            allow=(0, 5))
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_iters": info.iters_total, "copy_bytes_each_way": 1 << 30}))
+        return
 
     def step():
         ctx.set_galaxies(xyz_d)
@@ -169,8 +299,9 @@ def main():
     per_kernel = {}
     if prof:
         for k, v in prof.items():
-            per_kernel[k] = dict(launches=v["launches"], avg_us=1e3 * v["ms"] / v["launches"],
-                                 gbs=v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None)
+            per_kernel[k] = dict(launches=v["launches"], skipped=v["skipped"],
+                                 avg_us=round(1e3 * v["ms"] / v["launches"], 2),
+                                 gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
         solve_kernels = {k: v for k, v in prof.items() if k not in ("deposit", "supersample")}
         dom = max(solve_kernels, key=lambda k: solve_kernels[k]["ms"])
         d = prof[dom]
@@ -213,6 +344,9 @@ def main():
         cpu = cpu_baseline(wl, ptab, w, len(cat.xyz), iters_ref)
         log(f"[bench] cpu baseline {cpu['value']:.3e} solves/s ({time.perf_counter() - t:.1f} s)")
 
+    serving = serve(args.serve, args.tol) if args.serve else None
+    batch = batch_run(args.batch, args.tol) if args.batch else None
+
     lat_ms = sorted(1e3 * x for x in lat)
     res = {
         "metric": "Wiener-CG solves/s at 512^3 to 1e-6 rel. L2 (mixed vs FP64); p50/p99 latency",
@@ -241,6 +375,8 @@ def main():
         "kernels": per_kernel,
         "fp64": fp64,
         "cpu_baseline": cpu,
+        "serving": serving,
+        "batch": batch,
     }
     print(json.dumps(res))
 

@@ -228,11 +228,14 @@ typedef enum {
   WF_PROF_DEPOSIT, WF_PROF_SUPERSAMPLE
 } wf_prof_kind;
 
-/* Per class: launches, summed device time (HIP events recorded on the
+/* Per class: active launches, summed device time (HIP events recorded on the
  * context's stream around every launch) and algorithmic HBM bytes (the bytes
- * the pass must read and write once: inputs, outputs, the half spectrum). */
+ * the pass must read and write once: inputs, outputs, the half spectrum).
+ * Launches that found their solve already stopped (shorter than a quarter of
+ * the class's median) are counted in `skipped` and left out of the totals. */
 typedef struct {
   int64_t launches[WF_PROF_KINDS];
+  int64_t skipped[WF_PROF_KINDS];
   double ms[WF_PROF_KINDS];
   double bytes[WF_PROF_KINDS];
 } wf_profile;

@@ -57,12 +57,12 @@ PROF_NAMES = ["zfwd_f32", "yfwd_f32", "xlam_f32", "yinv_f32", "zinv_f32", "updat
 
 
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * PROF_KINDS), ("ms", C.c_double * PROF_KINDS),
-                ("bytes", C.c_double * PROF_KINDS)]
+    _fields_ = [("launches", C.c_int64 * PROF_KINDS), ("skipped", C.c_int64 * PROF_KINDS),
+                ("ms", C.c_double * PROF_KINDS), ("bytes", C.c_double * PROF_KINDS)]
 
     def as_dict(self):
-        return {PROF_NAMES[k]: dict(launches=int(self.launches[k]), ms=float(self.ms[k]),
-                                    bytes=float(self.bytes[k]))
+        return {PROF_NAMES[k]: dict(launches=int(self.launches[k]), skipped=int(self.skipped[k]),
+                                    ms=float(self.ms[k]), bytes=float(self.bytes[k]))
                 for k in range(PROF_KINDS) if self.launches[k]}
 
 

@@ -545,11 +545,7 @@ wf_status wf_profile_read(wf_ctx* c, wf_profile* out) {
   if (!s.ok()) return finish(c, s);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return finish(c, fail(WF_EDEVICE, "sync failed"));
   c->prof.harvest();
-  for (int k = 0; k < WF_PROF_KINDS; ++k) {
-    out->launches[k] = c->prof.launches[k];
-    out->ms[k] = c->prof.ms[k];
-    out->bytes[k] = c->prof.bytes[k];
-  }
+  c->prof.totals(out->launches, out->skipped, out->ms, out->bytes);
   return WF_OK;
 }
 

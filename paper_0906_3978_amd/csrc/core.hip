@@ -51,9 +51,28 @@ Profiler::~Profiler() {
 
 void Profiler::clear() {
   for (int k = 0; k < WF_PROF_KINDS; ++k) {
-    launches[k] = 0;
-    ms[k] = 0.0;
-    bytes[k] = 0.0;
+    dur[k].clear();
+    byt[k].clear();
+  }
+}
+
+void Profiler::totals(int64_t* launches, int64_t* skipped, double* ms, double* bytes) const {
+  for (int k = 0; k < WF_PROF_KINDS; ++k) {
+    launches[k] = skipped[k] = 0;
+    ms[k] = bytes[k] = 0.0;
+    if (dur[k].empty()) continue;
+    std::vector<float> t = dur[k];
+    std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+    const float cut = 0.25f * t[t.size() / 2];
+    for (size_t i = 0; i < dur[k].size(); ++i) {
+      if (dur[k][i] < cut) {
+        skipped[k] += 1;
+        continue;
+      }
+      launches[k] += 1;
+      ms[k] += dur[k][i];
+      bytes[k] += byt[k][i];
+    }
   }
 }
 
@@ -83,9 +102,8 @@ void Profiler::harvest() {
   for (auto& pr : pending) {
     float t = 0.f;
     if (hipEventElapsedTime(&t, pr.a, pr.b) == hipSuccess) {
-      launches[pr.kind] += 1;
-      ms[pr.kind] += t;
-      bytes[pr.kind] += pr.bytes;
+      dur[pr.kind].push_back(t);
+      byt[pr.kind].push_back(pr.bytes);
     }
     pool.push_back(pr.a);
     pool.push_back(pr.b);

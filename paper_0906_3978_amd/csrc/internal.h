@@ -68,9 +68,11 @@ struct Profiler {
   };
   std::vector<hipEvent_t> pool;
   std::vector<Pair> pending;
-  int64_t launches[WF_PROF_KINDS] = {};
-  double ms[WF_PROF_KINDS] = {};
-  double bytes[WF_PROF_KINDS] = {};
+  std::vector<float> dur[WF_PROF_KINDS];     // ms of every harvested launch
+  std::vector<double> byt[WF_PROF_KINDS];
+  // Totals over active launches: a launch shorter than a quarter of its
+  // class's median found its right-hand side already stopped and is skipped.
+  void totals(int64_t* launches, int64_t* skipped, double* ms, double* bytes) const;
   ~Profiler();
   void clear();
   int begin(int kind, double bytes, hipStream_t s);
