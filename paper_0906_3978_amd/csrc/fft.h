@@ -155,14 +155,77 @@ __device__ __forceinline__ void fft_stage(cplx<T>* lds, const cplx<T>* __restric
   __syncthreads();
 }
 
-template <typename T, int N, int NB, int NT, bool BF, int DIR, int I = 0>
+template <typename T, int N, int NB, int NT, bool BF, int DIR, int I = 0,
+          int IEND = Plan<N>::len>
 __device__ __forceinline__ void fft_tile(cplx<T>* lds, const cplx<T>* __restrict__ tw) {
-  if constexpr (I < Plan<N>::len) {
+  if constexpr (I < IEND) {
     constexpr int R = plan_radix<N>(DIR, I);
     constexpr int NS = plan_ns<N>(DIR, I);
     fft_stage<T, N, R, NS, NB, NT, BF, DIR>(lds, tw);
-    fft_tile<T, N, NB, NT, BF, DIR, I + 1>(lds, tw);
+    fft_tile<T, N, NB, NT, BF, DIR, I + 1, IEND>(lds, tw);
   }
+}
+
+// Copies the twiddle table into LDS (callers synchronise before use).
+template <typename T, int N, int NT>
+__device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __restrict__ src) {
+  for (int i = threadIdx.x; i < N; i += NT) dst[i] = src[i];
+}
+
+// Element index (along the FFT axis) of value r of butterfly `bf` in the last
+// forward stage of a batch-fast tile; the same thread's values after that
+// stage are the inputs of the first inverse stage.
+template <int N, int NB> __device__ __forceinline__ int lam_stage_index(int bf, int r) {
+  constexpr int R = Plan<N>::r[Plan<N>::len - 1];
+  return bf / NB + r * (N / R);
+}
+
+// Forward FFT, multiply by a per-element diagonal, inverse FFT, on a
+// batch-fast tile.  The last forward stage, the diagonal and the first
+// inverse stage run on the same registers: that thread holds outputs
+// j + r N/R of the forward transform, exactly the inputs of its inverse
+// butterfly.  lamv[i][r] is the diagonal at element lam_stage_index(bf_i, r).
+template <typename T, int N, int NB, int NT>
+__device__ __forceinline__ void fft_tile_diag(cplx<T>* lds, const cplx<T>* __restrict__ tw,
+                                              const T (*lamv)[Plan<N>::r[Plan<N>::len - 1]]) {
+  using V = cplx<T>;
+  constexpr int L = Plan<N>::len;
+  constexpr int R = Plan<N>::r[L - 1];
+  constexpr int NS = N / R;  // radices already applied before the last stage
+  constexpr int NBF = NB * (N / R);
+  constexpr int PER = (NBF + NT - 1) / NT;
+  fft_tile<T, N, NB, NT, true, -1, 0, L - 1>(lds, tw);
+  V v[PER][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int bf = tid + i * NT;
+    if ((NBF % NT == 0) || bf < NBF) {
+      const int b = bf % NB, j = bf / NB;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = lds[tile_addr<N, NB, true>(b, j + r * (N / R))];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[r * j]);
+      }
+      dft<R, -1>(v[i]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = V{v[i][r].x * lamv[i][r], v[i][r].y * lamv[i][r]};
+      dft<R, +1>(v[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int bf = tid + i * NT;
+    if ((NBF % NT == 0) || bf < NBF) {
+      const int b = bf % NB, j = bf / NB;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[tile_addr<N, NB, true>(b, j * R + r)] = v[i][r];
+    }
+  }
+  __syncthreads();
+  fft_tile<T, N, NB, NT, true, +1, 1, L>(lds, tw);
 }
 
 }  // namespace wf

@@ -69,10 +69,12 @@ __global__ __launch_bounds__(NT) void k_zfwd(ZfwdArgs<T> a) {
   constexpr int ITEMS = NB * N / RW;
   constexpr int PER = (ITEMS + NT - 1) / NT;
   __shared__ __align__(16) V lds[NB * N];
+  __shared__ V twl[N];
   const int rhs = blockIdx.y;
   CgState* st = a.st ? a.st + rhs : nullptr;
   if (st && skip_rhs(st, a.skip)) return;
   const int64_t row0 = (int64_t)blockIdx.x * NB * 2;
+  load_twiddles<T, N, NT>(twl, a.tw);
 
   T beta = T(0);
   bool first = true;
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(NT) void k_zfwd(ZfwdArgs<T> a) {
     }
   }
   __syncthreads();
-  fft_tile<T, N, NB, NT, false, -1>(lds, a.tw);
+  fft_tile<T, N, NB, NT, false, -1>(lds, twl);
 
   // split the two real rows: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
   V* om = a.out_main + rhs * a.rhs_main;
@@ -173,11 +175,13 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
   constexpr int NB = z_nb<T, N>();
   constexpr int H = N / 2;
   __shared__ __align__(16) V lds[NB * N];
+  __shared__ V twl[N];
   __shared__ double red[NT / 64];
   const int rhs = blockIdx.y;
   CgState* st = a.st ? a.st + rhs : nullptr;
   if (st && skip_rhs(st, a.skip)) return;
   const int64_t row0 = (int64_t)blockIdx.x * NB * 2;
+  load_twiddles<T, N, NT>(twl, a.tw);
   const V* im = a.in_main + rhs * a.rhs_main;
   const V* inq = a.in_nyq + rhs * a.rhs_nyq;
 
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
     lds[b * N + H] = V{inq[r0].x, inq[r0 + 1].x};
   }
   __syncthreads();
-  fft_tile<T, N, NB, NT, false, +1>(lds, a.tw);
+  fft_tile<T, N, NB, NT, false, +1>(lds, twl);
 
   constexpr int ITEMS3 = NB * N / RW;
   constexpr int PER3 = (ITEMS3 + NT - 1) / NT;
@@ -281,17 +285,18 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
 // ---------------------------------------------------------------------------
 // strided passes (y or x axis)
 // ---------------------------------------------------------------------------
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__(NT) void k_strided(StrArgs<T> a) {
+template <typename T, int N, int MODE, int TB, int NTS>
+__global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
+  constexpr int NT = NTS;
   using V = cplx<T>;
   using R = vec16<T>;
-  constexpr int TB = str_tb<T, N>();
   constexpr int CW = 16 / sizeof(V);
   constexpr bool VEC = (TB % CW) == 0;        // TB adjacent columns per row
   constexpr int G = VEC ? CW : 1;             // complex values moved per access
   constexpr int ITEMS = TB * N / G;
   constexpr int PER = (ITEMS + NT - 1) / NT;
   __shared__ __align__(16) V lds[TB * N];
+  __shared__ V twl[N];
   const int rhs = blockIdx.y;
   if (a.st && skip_rhs(a.st + rhs, a.skip)) return;
   int blk = blockIdx.x;
@@ -355,23 +360,36 @@ __global__ __launch_bounds__(NT) void k_strided(StrArgs<T> a) {
       }
     }
   }
-  __syncthreads();
-  if constexpr (MODE == SM_INV) fft_tile<T, N, TB, NT, true, +1>(lds, a.tw);
-  else fft_tile<T, N, TB, NT, true, -1>(lds, a.tw);
-
+  load_twiddles<T, N, NT>(twl, a.tw);
   if constexpr (MODE == SM_FWD_LAM_INV) {
+    // Lambda[|m|^2] of the elements this thread holds between the forward and
+    // the inverse transform, gathered from the L2-resident table before the
+    // forward FFT so that the loads complete under it.
+    constexpr int RL = Plan<N>::r[Plan<N>::len - 1];
+    constexpr int NBF = TB * (N / RL);
+    constexpr int PL = (NBF + NT - 1) / NT;
+    T lamv[PL][RL];
     const int mo = s.lam_outer_signed ? signed_m(outer, N) : 0;
     const int base = mo * mo + s.lam_const;
-    for (int e = threadIdx.x; e < TB * N; e += NT) {
-      const int b = e % TB, i = e / TB;
-      const int mi = signed_m(i, N);
-      const int mb = s.lam_batch_signed ? signed_m(b0 + b, N) : (b0 + b);
-      const T l = a.lam[base + mi * mi + mb * mb];
-      const V v = lds[e];
-      lds[e] = V{v.x * l, v.y * l};
+#pragma unroll
+    for (int c = 0; c < PL; ++c) {
+      const int bf = threadIdx.x + c * NT;
+      if (NBF % NT == 0 || bf < NBF) {
+        const int b = bf % TB;
+        const int mb = s.lam_batch_signed ? signed_m(b0 + b, N) : (b0 + b);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const int mi = signed_m(lam_stage_index<N, TB>(bf, r), N);
+          lamv[c][r] = a.lam[base + mi * mi + mb * mb];
+        }
+      }
     }
     __syncthreads();
-    fft_tile<T, N, TB, NT, true, +1>(lds, a.tw);
+    fft_tile_diag<T, N, TB, NT>(lds, twl, lamv);
+  } else {
+    __syncthreads();
+    if constexpr (MODE == SM_INV) fft_tile<T, N, TB, NT, true, +1>(lds, twl);
+    else fft_tile<T, N, TB, NT, true, -1>(lds, twl);
   }
 
   V* out = s.out + rhs * s.out_rhs + outer * s.out_outer + b0 * s.out_batch;
@@ -515,6 +533,9 @@ bool fft_length_supported(int n, bool fp64) {
   }
 }
 
+// Strided tiles: TB = str_tb<T, N> adjacent columns, 512 threads.
+constexpr int NT_STRIDED = 512;
+
 int strided_tb(int n, bool fp64) {
   switch (n) {
 #define X(L) \
@@ -574,19 +595,26 @@ static hipError_t zinv_n(int mode, const ZinvArgs<T>& a, int64_t nrows, int nrhs
   return hipGetLastError();
 }
 
-template <typename T, int N>
-static hipError_t strided_n(int mode, const StrArgs<T>& a, int nrhs, hipStream_t s) {
+template <typename T, int N, int TBV, int NTV>
+static hipError_t strided_v(int mode, const StrArgs<T>& a, int nrhs, hipStream_t s) {
   dim3 grid((unsigned)(a.nblk0 + a.nblk1), (unsigned)nrhs);
   switch (mode) {
-    case SM_FWD: hipLaunchKernelGGL((k_strided<T, N, SM_FWD>), grid, dim3(NT), 0, s, a); break;
-    case SM_INV: hipLaunchKernelGGL((k_strided<T, N, SM_INV>), grid, dim3(NT), 0, s, a); break;
+    case SM_FWD: hipLaunchKernelGGL((k_strided<T, N, SM_FWD, TBV, NTV>), grid, dim3(NTV), 0, s, a); break;
+    case SM_INV: hipLaunchKernelGGL((k_strided<T, N, SM_INV, TBV, NTV>), grid, dim3(NTV), 0, s, a); break;
     case SM_FWD_LAM_INV:
-      hipLaunchKernelGGL((k_strided<T, N, SM_FWD_LAM_INV>), grid, dim3(NT), 0, s, a);
+      hipLaunchKernelGGL((k_strided<T, N, SM_FWD_LAM_INV, TBV, NTV>), grid, dim3(NTV), 0, s, a);
       break;
-    case SM_FWD_CROP: hipLaunchKernelGGL((k_strided<T, N, SM_FWD_CROP>), grid, dim3(NT), 0, s, a); break;
+    case SM_FWD_CROP:
+      hipLaunchKernelGGL((k_strided<T, N, SM_FWD_CROP, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t strided_n(int mode, const StrArgs<T>& a, int nrhs, hipStream_t s) {
+  return strided_v<T, N, str_tb<T, N>(), NT_STRIDED>(mode, a, nrhs, s);
 }
 
 template <> hipError_t launch_zfwd<double>(int n, int mode, const ZfwdArgs<double>& a, int64_t nrows,
