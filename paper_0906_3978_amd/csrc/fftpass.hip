@@ -24,11 +24,13 @@ template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_t
 template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
 template <typename T> using vec16 = typename Vec16<T>::type;
 
+// 16-byte global accesses; every array a pass touches is streamed once, so
+// they bypass the caches (nontemporal).
 template <typename T> __device__ __forceinline__ vec16<T> ld16(const T* p) {
-  return *reinterpret_cast<const vec16<T>*>(p);
+  return __builtin_nontemporal_load(reinterpret_cast<const vec16<T>*>(p));
 }
 template <typename T> __device__ __forceinline__ void st16(T* p, vec16<T> v) {
-  *reinterpret_cast<vec16<T>*>(p) = v;
+  __builtin_nontemporal_store(v, reinterpret_cast<vec16<T>*>(p));
 }
 
 // ---------------------------------------------------------------------------

@@ -87,6 +87,7 @@ hipError_t launch_finalize(int kind, const double* partials, int nparts, int ski
 // ---- vector kernels --------------------------------------------------------
 constexpr int VEC_THREADS = 256;
 int vec_blocks(int64_t m);
+int update_blocks(int64_t m, bool fp64);   // blocks (= partials per RHS) of the update kernel
 
 // x = 0; r = (T) src; rho = r.r; bnorm; starts a CG solve
 template <typename T> hipError_t launch_cg_init(T* x, T* r, const double* src, int64_t m,

@@ -56,7 +56,7 @@ Status cg_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hi
                  6.0 * sizeof(T) * od.g.m * nr, s);
     WF_HIP(launch_cg_update<T>(v.x, v.r, v.p, v.q, od.g.m, od.g.m, parts, st, nr, s));
   }
-  WF_HIP(launch_finalize(FIN_RR, parts, vec_blocks(od.g.m), SKIP_DONE, st, nr, s));
+  WF_HIP(launch_finalize(FIN_RR, parts, update_blocks(od.g.m, sizeof(T) == 8), SKIP_DONE, st, nr, s));
   return {};
 }
 
