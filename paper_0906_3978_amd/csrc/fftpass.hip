@@ -32,6 +32,15 @@ template <typename T> __device__ __forceinline__ vec16<T> ld16(const T* p) {
 template <typename T> __device__ __forceinline__ void st16(T* p, vec16<T> v) {
   __builtin_nontemporal_store(v, reinterpret_cast<vec16<T>*>(p));
 }
+// Cached 16-byte accesses (the y passes run faster with them).
+template <bool NTA, typename T> __device__ __forceinline__ vec16<T> ld16x(const T* p) {
+  if constexpr (NTA) return ld16(p);
+  else return *reinterpret_cast<const vec16<T>*>(p);
+}
+template <bool NTA, typename T> __device__ __forceinline__ void st16x(T* p, vec16<T> v) {
+  if constexpr (NTA) st16(p, v);
+  else *reinterpret_cast<vec16<T>*>(p) = v;
+}
 
 // ---------------------------------------------------------------------------
 // tile geometry
@@ -290,6 +299,7 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
 template <typename T, int N, int MODE, int TB, int NTS>
 __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   constexpr int NT = NTS;
+  constexpr bool NTA = (MODE == SM_FWD_LAM_INV);  // nontemporal in the x pass only
   using V = cplx<T>;
   using R = vec16<T>;
   constexpr int CW = 16 / sizeof(V);
@@ -318,7 +328,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
         const int q = threadIdx.x + c * NT;
         if (ITEMS % NT == 0 || q < ITEMS) {
           const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-          buf[c] = ld16(reinterpret_cast<const T*>(in + i * s.in_axis + b));
+          buf[c] = ld16x<NTA>(reinterpret_cast<const T*>(in + i * s.in_axis + b));
         }
       }
 #pragma unroll
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
       if (IT % NT == 0 || q < IT) {
         const int b = q / (N / AV), i = (q - b * (N / AV)) * AV;
         if constexpr (AV == CW && CW > 1) {
-          const R v = ld16(reinterpret_cast<const T*>(in + b * s.in_batch + i));
+          const R v = ld16x<NTA>(reinterpret_cast<const T*>(in + b * s.in_batch + i));
 #pragma unroll
           for (int j = 0; j < AV; ++j) buf[c][j] = V{v[2 * j], v[2 * j + 1]};
         } else {
@@ -410,7 +420,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
         const int q = threadIdx.x + c * NT;
         if (ITEMS % NT == 0 || q < ITEMS) {
           const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-          st16(reinterpret_cast<T*>(out + i * s.out_axis + b), *reinterpret_cast<const R*>(lds + q * CW));
+          st16x<NTA>(reinterpret_cast<T*>(out + i * s.out_axis + b), *reinterpret_cast<const R*>(lds + q * CW));
         }
       }
     } else {
@@ -432,7 +442,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           v[2 * j] = x.x;
           v[2 * j + 1] = x.y;
         }
-        st16(reinterpret_cast<T*>(out + b * s.out_batch + i), v);
+        st16x<NTA>(reinterpret_cast<T*>(out + b * s.out_batch + i), v);
       } else {
         out[b * s.out_batch + i] = lds[i * TB + b];
       }
