@@ -326,13 +326,13 @@ wf_status wf_apply_operator(wf_ctx* c, wf_precision prec, const double* v, doubl
     WF_HIP(hipMemcpyAsync(sw.state.p, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
     WF_TRY(upload(sw.x64.p, v, (size_t)g.m * 8, mem, c->stream));
     if (prec == WF_FP64) {
-      WF_TRY(operator_passes<double>(c->od, ZIN_REAL, sw.x64.as<double>(), nullptr,
+      WF_TRY(operator_passes<double>(c->od, ZIN_REAL, sw.x64.as<double>(), nullptr, nullptr,
                                      sw.spec64.as<double2>(), ZOUT_APPLY, sw.q64.as<double>(),
                                      sw.x64.as<double>(), nullptr, sw.state.as<CgState>(),
                                      sw.partials.as<double>(), 1, SKIP_NONE, c->stream));
     } else {
       WF_HIP(launch_f64_to_f32(sw.x32.as<float>(), sw.x64.as<double>(), g.m, c->stream));
-      WF_TRY(operator_passes<float>(c->od, ZIN_REAL, sw.x32.as<float>(), nullptr,
+      WF_TRY(operator_passes<float>(c->od, ZIN_REAL, sw.x32.as<float>(), nullptr, nullptr,
                                     sw.spec32.as<float2>(), ZOUT_APPLY, sw.q32.as<float>(),
                                     sw.x32.as<float>(), nullptr, sw.state.as<CgState>(),
                                     sw.partials.as<double>(), 1, SKIP_NONE, c->stream));

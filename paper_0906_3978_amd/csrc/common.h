@@ -53,7 +53,8 @@ struct CgState {
   uint32_t ticket;   // last-block counter of the reductions
   int32_t updates;   // reliable updates done
   int32_t max_updates;
-  int32_t pad;
+  int32_t pending;   // 1: x still lacks alpha p of the last iteration (applied by the next
+                     // z pass, a reliable-update fold or a flush)
 };
 
 enum : int32_t {

@@ -299,7 +299,7 @@ static StrArgs<T> str_args(const OperatorData& od, cplx<T>* spec, bool xpass, co
 }
 
 template <typename T>
-Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T* p,
+Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T* p, T* x,
                        cplx<T>* spec, int zout_mode, T* out, const T* aux, const double* bvec,
                        CgState* st, double* partials, int nrhs, int skip, hipStream_t s) {
   const Grid& g = od.g;
@@ -309,6 +309,7 @@ Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T
   ZfwdArgs<T> zf{};
   zf.in = in_or_r;
   zf.p = p;
+  zf.x = x;
   zf.out_main = spec;
   zf.out_nyq = spec + g.spec_main;
   zf.nkz_out = g.n / 2;
@@ -319,7 +320,8 @@ Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T
   zf.st = (zin_mode == ZIN_CGP || skip != SKIP_NONE) ? st : nullptr;
   zf.skip = skip;
   {
-    ProfScope ps(od.prof, kbase + 0, (zin_mode == ZIN_CGP ? 3 * vb : vb) + sb, s);
+    // CG: r, p, x in; p, x, spectrum out
+    ProfScope ps(od.prof, kbase + 0, (zin_mode == ZIN_CGP ? 5 * vb : vb) + sb, s);
     WF_HIP(launch_zfwd<T>(g.n, zin_mode, zf, g.nrows, nrhs, s));
   }
   {
@@ -367,10 +369,10 @@ Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T
   return {};
 }
 
-template Status operator_passes<float>(const OperatorData&, int, const float*, float*, cplx<float>*,
-                                       int, float*, const float*, const double*, CgState*, double*,
-                                       int, int, hipStream_t);
-template Status operator_passes<double>(const OperatorData&, int, const double*, double*,
+template Status operator_passes<float>(const OperatorData&, int, const float*, float*, float*,
+                                       cplx<float>*, int, float*, const float*, const double*,
+                                       CgState*, double*, int, int, hipStream_t);
+template Status operator_passes<double>(const OperatorData&, int, const double*, double*, double*,
                                         cplx<double>*, int, double*, const double*, const double*,
                                         CgState*, double*, int, int, hipStream_t);
 
@@ -499,7 +501,7 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
   return {};
 }
 
-double model_bytes_iteration(bool fp64) { return fp64 ? 160.0 : 80.0; }
+double model_bytes_iteration(bool fp64) { return fp64 ? 152.0 : 76.0; }
 double model_bytes_residual() { return 104.0; }
 
 }  // namespace wf

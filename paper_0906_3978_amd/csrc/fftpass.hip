@@ -87,11 +87,13 @@ __global__ __launch_bounds__(NT) void k_zfwd(ZfwdArgs<T> a) {
   const int64_t row0 = (int64_t)blockIdx.x * NB * 2;
   load_twiddles<T, N, NT>(twl, a.tw);
 
-  T beta = T(0);
-  bool first = true;
+  T beta = T(0), alpha = T(0);
+  bool first = true, pending = false;
   if constexpr (MODE == ZIN_CGP) {
     first = st->first != 0;
     beta = (T)st->beta;
+    alpha = (T)st->alpha;
+    pending = st->pending != 0;
   }
   R va[PER], vb[PER];
 #pragma unroll
@@ -110,8 +112,14 @@ __global__ __launch_bounds__(NT) void k_zfwd(ZfwdArgs<T> a) {
         va[c] = ld16(r + i0);
         vb[c] = ld16(r + i0 + N);
         if (!first) {
-          va[c] += beta * ld16(p + i0);
-          vb[c] += beta * ld16(p + i0 + N);
+          const R p0 = ld16(p + i0), p1 = ld16(p + i0 + N);
+          if (pending) {  // x += alpha p of the previous iteration
+            T* x = a.x + rhs * a.rhs_in;
+            st16(x + i0, ld16(x + i0) + alpha * p0);
+            st16(x + i0 + N, ld16(x + i0 + N) + alpha * p1);
+          }
+          va[c] += beta * p0;
+          vb[c] += beta * p1;
         }
         st16(p + i0, va[c]);
         st16(p + i0 + N, vb[c]);
@@ -474,6 +482,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partials, int np
   const double tot = block_sum((s0 + s1) + (s2 + s3), red);
   if (threadIdx.x != 0) return;
   if constexpr (KIND == FIN_PQ) {
+    st->pending = 0;  // the z pass of this iteration applied it
     st->pq = tot;
     if (!(tot > 0.0) || !isfinite(tot)) {
       st->done = 1;
@@ -504,6 +513,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partials, int np
     st->rho_old = st->rho;
     st->rho = rho_new;
     st->first = 0;
+    st->pending = 1;
   } else {  // FIN_RES
     st->outer_rr = tot;
   }

@@ -131,7 +131,7 @@ Status download(void* dst, const void* src, size_t bytes, wf_mem mem, hipStream_
 
 // Operator pipeline (five sweeps) on `nrhs` vectors laid out with stride g.m.
 template <typename T>
-Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T* p,
+Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T* p, T* x,
                        cplx<T>* spec, int zout_mode, T* out, const T* aux,
                        const double* bvec, CgState* st, double* partials, int nrhs,
                        int skip, hipStream_t s);

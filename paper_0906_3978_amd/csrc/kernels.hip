@@ -46,6 +46,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_cg_init(T* x, T* r, const doubl
       st->rel = 1.0;
       st->iter = 0;
       st->first = 1;
+      st->pending = 0;
       st->status = CG_RUNNING;
       st->done = (tot == 0.0 || st->max_iter <= 0) ? 1 : 0;
       if (tot == 0.0) st->status = CG_CONVERGED;
@@ -59,15 +60,14 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
 
-// x += alpha p, r -= alpha q and the block partial of r.r.  Each block owns
-// a contiguous run of VEC_THREADS * K 16-byte vectors; every load of a thread
-// is issued before the first use, and the streams bypass the caches
-// (nontemporal): measured on MI355X this moves ~20% more bytes per second
-// than a grid-stride loop.
+// r -= alpha q and the block partial of r.r (x += alpha p waits for the next
+// z pass, which reads p anyway).  Each block owns a contiguous run of
+// VEC_THREADS * K 16-byte vectors; every load of a thread is issued before
+// the first use, and the streams bypass the caches (nontemporal): measured on
+// MI355X this moves ~20% more bytes per second than a grid-stride loop.
 template <typename T, int K>
-__global__ __launch_bounds__(VEC_THREADS) void k_cg_update(T* x, T* r, const T* p, const T* q,
-                                                           int64_t m, int64_t rs, double* partials,
-                                                           CgState* st_all) {
+__global__ __launch_bounds__(VEC_THREADS) void k_cg_update(T* r, const T* q, int64_t m, int64_t rs,
+                                                           double* partials, CgState* st_all) {
   using R = typename Vec16<T>::type;
   constexpr int RW = 16 / sizeof(T);
   __shared__ double red[VEC_THREADS / 64];
@@ -75,9 +75,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_cg_update(T* x, T* r, const T* 
   CgState* st = st_all + rhs;
   if (st->done) return;
   const T alpha = (T)st->alpha;
-  R* xx = reinterpret_cast<R*>(x + rhs * rs);
   R* rr = reinterpret_cast<R*>(r + rhs * rs);
-  const R* pp = reinterpret_cast<const R*>(p + rhs * rs);
   const R* qq = reinterpret_cast<const R*>(q + rhs * rs);
   const int64_t mv = m / RW;
   const int64_t base = (int64_t)blockIdx.x * VEC_THREADS * K + threadIdx.x;
@@ -85,30 +83,25 @@ __global__ __launch_bounds__(VEC_THREADS) void k_cg_update(T* x, T* r, const T* 
   if constexpr (K == 1) {
     if (base < mv) {
       const R rn = __builtin_nontemporal_load(rr + base) - alpha * __builtin_nontemporal_load(qq + base);
-      const R xn = __builtin_nontemporal_load(xx + base) + alpha * __builtin_nontemporal_load(pp + base);
       __builtin_nontemporal_store(rn, rr + base);
-      __builtin_nontemporal_store(xn, xx + base);
 #pragma unroll
       for (int j = 0; j < RW; ++j) acc += (double)rn[j] * (double)rn[j];
     }
   } else {
     // whole blocks only (the launcher checks that K * VEC_THREADS divides mv)
     (void)mv;
-    R xv[K], rv[K], pv[K], qv[K];
+    R rv[K], qv[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       const int64_t i = base + c * VEC_THREADS;
       rv[c] = __builtin_nontemporal_load(rr + i);
       qv[c] = __builtin_nontemporal_load(qq + i);
-      xv[c] = __builtin_nontemporal_load(xx + i);
-      pv[c] = __builtin_nontemporal_load(pp + i);
     }
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       const int64_t i = base + c * VEC_THREADS;
       const R rn = rv[c] - alpha * qv[c];
       __builtin_nontemporal_store(rn, rr + i);
-      __builtin_nontemporal_store(xv[c] + alpha * pv[c], xx + i);
 #pragma unroll
       for (int j = 0; j < RW; ++j) acc += (double)rn[j] * (double)rn[j];
     }
@@ -116,6 +109,37 @@ __global__ __launch_bounds__(VEC_THREADS) void k_cg_update(T* x, T* r, const T* 
   const double part = block_sum(acc, red);
   if (threadIdx.x == 0) partials[(int64_t)rhs * gridDim.x + blockIdx.x] = part;
 }
+
+template <typename T>
+__global__ __launch_bounds__(VEC_THREADS) void k_cg_flush(T* x, const T* p, int64_t m, int64_t rs,
+                                                          const CgState* st_all) {
+  const int rhs = blockIdx.y;
+  const CgState* st = st_all + rhs;
+  if (!st->pending) return;
+  const T alpha = (T)st->alpha;
+  T* xx = x + rhs * rs;
+  const T* pp = p + rhs * rs;
+  const int64_t stride = (int64_t)gridDim.x * VEC_THREADS;
+  for (int64_t i = (int64_t)blockIdx.x * VEC_THREADS + threadIdx.x; i < m; i += stride)
+    xx[i] = xx[i] + alpha * pp[i];
+}
+
+__global__ void k_clear_pending(CgState* st_all) {
+  if (threadIdx.x == 0) st_all[blockIdx.x].pending = 0;
+}
+
+template <typename T>
+hipError_t launch_cg_flush(T* x, const T* p, int64_t m, int64_t rs, CgState* st, int nrhs,
+                           hipStream_t s) {
+  dim3 grid(vec_blocks(m), nrhs);
+  hipLaunchKernelGGL(k_cg_flush<T>, grid, dim3(VEC_THREADS), 0, s, x, p, m, rs, st);
+  hipLaunchKernelGGL(k_clear_pending, dim3(nrhs), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_flush<float>(float*, const float*, int64_t, int64_t, CgState*, int,
+                                           hipStream_t);
+template hipError_t launch_cg_flush<double>(double*, const double*, int64_t, int64_t, CgState*, int,
+                                            hipStream_t);
 
 // vectors per thread of the update kernel: long runs for large grids, one
 // vector for small ones (enough blocks to fill 256 CUs)
@@ -143,19 +167,19 @@ template hipError_t launch_cg_init<double>(double*, double*, const double*, int6
                                            double*, CgState*, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_cg_update(T* x, T* r, const T* p, const T* q, int64_t m, int64_t rs,
-                            double* partials, CgState* st, int nrhs, hipStream_t s) {
+hipError_t launch_cg_update(T* r, const T* q, int64_t m, int64_t rs, double* partials,
+                            CgState* st, int nrhs, hipStream_t s) {
   dim3 grid(update_blocks(m, sizeof(T) == 8), nrhs);
   if (update_k(m, 16 / sizeof(T)) == 8)
-    hipLaunchKernelGGL((k_cg_update<T, 8>), grid, dim3(VEC_THREADS), 0, s, x, r, p, q, m, rs, partials, st);
+    hipLaunchKernelGGL((k_cg_update<T, 8>), grid, dim3(VEC_THREADS), 0, s, r, q, m, rs, partials, st);
   else
-    hipLaunchKernelGGL((k_cg_update<T, 1>), grid, dim3(VEC_THREADS), 0, s, x, r, p, q, m, rs, partials, st);
+    hipLaunchKernelGGL((k_cg_update<T, 1>), grid, dim3(VEC_THREADS), 0, s, r, q, m, rs, partials, st);
   return hipGetLastError();
 }
-template hipError_t launch_cg_update<float>(float*, float*, const float*, const float*, int64_t,
-                                            int64_t, double*, CgState*, int, hipStream_t);
-template hipError_t launch_cg_update<double>(double*, double*, const double*, const double*,
-                                             int64_t, int64_t, double*, CgState*, int, hipStream_t);
+template hipError_t launch_cg_update<float>(float*, const float*, int64_t, int64_t, double*,
+                                            CgState*, int, hipStream_t);
+template hipError_t launch_cg_update<double>(double*, const double*, int64_t, int64_t, double*,
+                                             CgState*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // mixed precision: FP32 CG with FP64 reliable updates
@@ -197,6 +221,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_init(double* x64, double* r
       st->iter = 0;
       st->updates = 0;
       st->first = 1;
+      st->pending = 0;
       st->reliable = 1;
       if (tb == 0.0) {
         st->done = 1;
@@ -222,22 +247,25 @@ hipError_t launch_rel_init(double* x64, double* r64, const double* b, float* x32
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(VEC_THREADS) void k_rel_fold(double* x64, float* x32, int64_t m,
-                                                          int64_t rs, const CgState* st_all) {
+__global__ __launch_bounds__(VEC_THREADS) void k_rel_fold(double* x64, float* x32, const float* p32,
+                                                          int64_t m, int64_t rs,
+                                                          const CgState* st_all) {
   const int rhs = blockIdx.y;
-  if (st_all[rhs].status != CG_UPDATE) return;
+  const CgState* st = st_all + rhs;
+  if (st->status != CG_UPDATE) return;
+  const float alpha = st->pending ? (float)st->alpha : 0.f;
   const int64_t o = rhs * rs;
   const int64_t stride = (int64_t)gridDim.x * VEC_THREADS;
   for (int64_t i = (int64_t)blockIdx.x * VEC_THREADS + threadIdx.x; i < m; i += stride) {
-    x64[o + i] += (double)x32[o + i];
+    x64[o + i] += (double)(x32[o + i] + alpha * p32[o + i]);
     x32[o + i] = 0.f;
   }
 }
 
-hipError_t launch_rel_fold(double* x64, float* x32, int64_t m, int64_t rs, const CgState* st,
-                           int nrhs, hipStream_t s) {
+hipError_t launch_rel_fold(double* x64, float* x32, const float* p32, int64_t m, int64_t rs,
+                           const CgState* st, int nrhs, hipStream_t s) {
   dim3 grid(vec_blocks(m), nrhs);
-  hipLaunchKernelGGL(k_rel_fold, grid, dim3(VEC_THREADS), 0, s, x64, x32, m, rs, st);
+  hipLaunchKernelGGL(k_rel_fold, grid, dim3(VEC_THREADS), 0, s, x64, x32, p32, m, rs, st);
   return hipGetLastError();
 }
 
@@ -263,6 +291,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const dou
     const double tot = reduce_partials(parts, gridDim.x, red);
     if (threadIdx.x == 0) {
       st->updates += 1;
+      st->pending = 0;  // folded
       const double rel = sqrt(st->outer_rr) / st->bnorm;
       if (rel <= st->tol) {
         st->status = CG_CONVERGED;

@@ -15,6 +15,7 @@ enum ZoutMode : int { ZOUT_REAL = 0, ZOUT_CGQ = 1, ZOUT_RES = 2, ZOUT_APPLY = 3 
 template <typename T> struct ZfwdArgs {
   const T* in;              // ZIN_REAL: rows; ZIN_CGP: r
   T* p;                     // ZIN_CGP: search direction, updated in place
+  T* x;                     // ZIN_CGP: iterate, receives the pending alpha p
   const long long* gin;     // ZIN_I64: integer rows
   double unit;              // ZIN_I64: value of one integer unit
   cplx<T>* out_main;        // [row][nkz_out]
@@ -93,18 +94,22 @@ int update_blocks(int64_t m, bool fp64);   // blocks (= partials per RHS) of the
 template <typename T> hipError_t launch_cg_init(T* x, T* r, const double* src, int64_t m,
                                                 int64_t rhs_stride, double* partials,
                                                 CgState* st, int nrhs, hipStream_t s);
-// x += alpha p; r -= alpha q; block partials of r.r (then FIN_RR)
-template <typename T> hipError_t launch_cg_update(T* x, T* r, const T* p, const T* q, int64_t m,
+// r -= alpha q; block partials of r.r (then FIN_RR).  x += alpha p is left
+// pending for the next z pass (or a fold / flush).
+template <typename T> hipError_t launch_cg_update(T* r, const T* q, int64_t m,
                                                   int64_t rhs_stride, double* partials,
                                                   CgState* st, int nrhs, hipStream_t s);
+// x += alpha p for the RHS whose state has it pending, then clears it
+template <typename T> hipError_t launch_cg_flush(T* x, const T* p, int64_t m, int64_t rhs_stride,
+                                                 CgState* st, int nrhs, hipStream_t s);
 // mixed precision with reliable updates:
 // start: x64 = 0, r64 = b, x32 = 0, r32 = (float) b; bnorm, rho, rmax
 hipError_t launch_rel_init(double* x64, double* r64, const double* b, float* x32, float* r32,
                            int64_t m, int64_t rhs_stride, double* partials, CgState* st, int nrhs,
                            hipStream_t s);
-// RHS waiting for an update: x64 += x32, x32 = 0
-hipError_t launch_rel_fold(double* x64, float* x32, int64_t m, int64_t rhs_stride,
-                           const CgState* st, int nrhs, hipStream_t s);
+// RHS waiting for an update: x64 += x32 (+ the pending alpha p32), x32 = 0
+hipError_t launch_rel_fold(double* x64, float* x32, const float* p32, int64_t m,
+                           int64_t rhs_stride, const CgState* st, int nrhs, hipStream_t s);
 // RHS waiting for an update (after r64 = b - A64 x64): r32 = (float) r64, rho,
 // convergence test on the FP64 residual, resume or stop
 hipError_t launch_rel_reset(float* r32, const double* r64, int64_t m, int64_t rhs_stride,

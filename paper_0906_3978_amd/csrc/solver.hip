@@ -49,12 +49,12 @@ template <typename T>
 Status cg_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hipStream_t s) {
   CgState* st = sw.state.as<CgState>();
   double* parts = sw.partials.as<double>();
-  WF_TRY(operator_passes<T>(od, ZIN_CGP, v.r, v.p, v.spec, ZOUT_CGQ, v.q, v.p, nullptr, st, parts,
-                            nr, SKIP_DONE, s));
+  WF_TRY(operator_passes<T>(od, ZIN_CGP, v.r, v.p, v.x, v.spec, ZOUT_CGQ, v.q, v.p, nullptr, st,
+                            parts, nr, SKIP_DONE, s));
   {
     ProfScope ps(od.prof, sizeof(T) == 8 ? WF_PROF_UPDATE_F64 : WF_PROF_UPDATE_F32,
-                 6.0 * sizeof(T) * od.g.m * nr, s);
-    WF_HIP(launch_cg_update<T>(v.x, v.r, v.p, v.q, od.g.m, od.g.m, parts, st, nr, s));
+                 3.0 * sizeof(T) * od.g.m * nr, s);
+    WF_HIP(launch_cg_update<T>(v.r, v.q, od.g.m, od.g.m, parts, st, nr, s));
   }
   WF_HIP(launch_finalize(FIN_RR, parts, update_blocks(od.g.m, sizeof(T) == 8), SKIP_DONE, st, nr, s));
   return {};
@@ -88,12 +88,7 @@ Status iterate_reliable(const OperatorData& od, SolveWork& sw, int nr, int check
       update = update || sw.st_host[i].status == CG_UPDATE;
     }
     if (update) {
-      WF_HIP(launch_rel_fold(sw.x64.as<double>(), v.x, g.m, g.m, st, nr, s));
-      WF_TRY(operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr,
-                                     sw.spec64.as<double2>(), ZOUT_RES, sw.r64.as<double>(),
-                                     sw.x64.as<double>(), sw.b64.as<double>(), st, parts, nr,
-                                     SKIP_UNLESS_UPDATE, s));
-      WF_HIP(launch_rel_reset(v.r, sw.r64.as<double>(), g.m, g.m, parts, st, nr, s));
+      WF_TRY(solve_update(od, sw, nr, s));
       continue;
     }
     if (all) return {};
@@ -147,9 +142,12 @@ Status push_states(SolveWork& sw, const std::vector<CgState>& st, hipStream_t s)
   return {};
 }
 
-// r_true = b - A64 x into `out`; outer_rr = ||r_true||^2 per RHS.
+// FP64 CG: applies the pending x += alpha p, then r_true = b - A64 x into
+// `out`; outer_rr = ||r_true||^2 per RHS.
 Status true_residual(const OperatorData& od, SolveWork& sw, double* out, int nr, hipStream_t s) {
-  return operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr,
+  WF_HIP(launch_cg_flush<double>(sw.x64.as<double>(), sw.p64.as<double>(), od.g.m, od.g.m,
+                                 sw.state.as<CgState>(), nr, s));
+  return operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr, nullptr,
                                  sw.spec64.as<double2>(), ZOUT_RES, out, sw.x64.as<double>(),
                                  sw.b64.as<double>(), sw.state.as<CgState>(),
                                  sw.partials.as<double>(), nr, SKIP_NONE, s);
@@ -187,8 +185,10 @@ Status solve_update(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s
   const Grid& g = od.g;
   CgState* st = sw.state.as<CgState>();
   double* parts = sw.partials.as<double>();
-  WF_HIP(launch_rel_fold(sw.x64.as<double>(), sw.x32.as<float>(), g.m, g.m, st, nr, s));
-  WF_TRY(operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr, sw.spec64.as<double2>(),
+  WF_HIP(launch_rel_fold(sw.x64.as<double>(), sw.x32.as<float>(), sw.p32.as<float>(), g.m, g.m, st,
+                         nr, s));
+  WF_TRY(operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr, nullptr,
+                                 sw.spec64.as<double2>(),
                                  ZOUT_RES, sw.r64.as<double>(), sw.x64.as<double>(),
                                  sw.b64.as<double>(), st, parts, nr, SKIP_UNLESS_UPDATE, s));
   WF_HIP(launch_rel_reset(sw.r32.as<float>(), sw.r64.as<double>(), g.m, g.m, parts, st, nr, s));
