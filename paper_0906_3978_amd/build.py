@@ -29,6 +29,8 @@ COMMON = [
     f"-I{INCLUDE}", f"-I{CSRC}",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-Wno-unknown-pragmas",
+    # a variable read before it is set is a build error, not a warning
+    "-Werror=uninitialized", "-Werror=sometimes-uninitialized",
 ]
 
 

@@ -195,15 +195,15 @@ wf_status wf_set_power(wf_ctx* c, const double* p, int64_t len, wf_mem mem) {
       src = staging.as<double>();
     }
     WF_TRY(c->od.lam64.ensure(c->al, (size_t)len * 8));
-    WF_TRY(c->od.lam32.ensure(c->al, (size_t)len * 4));
+    WF_TRY(alloc_xlam(c->al, c->od));
     WF_TRY(clear_flag(c));
     const double h = g.box / g.n;
     WF_HIP(launch_lambda(src, len, h * h * h, 1.0 / (double)g.m, c->od.lam64.as<double>(),
-                         c->od.lam32.as<float>(), c->flag.as<int>(), c->stream));
+                         c->flag.as<int>(), c->stream));
     int bad = 0;
     WF_TRY(read_flag(c, &bad));
     if (bad) return fail(WF_EINVAL, "P(k) must be finite and > 0 for j >= 1");
-    return {};
+    return build_xlam(c->od, c->stream);
   };
   s = run();
   c->have_power = s.ok();

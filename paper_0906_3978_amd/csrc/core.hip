@@ -119,6 +119,19 @@ void Grid::set(int n_, double box_) {
   spec_main = (int64_t)n * n * (n / 2);
   spec_total = spec_main + (int64_t)n * n;
   lamlen = 3 * (int64_t)(n / 2) * (n / 2) + 1;
+  xlamlen = xlam_elems(n);
+}
+
+Status alloc_xlam(const Allocator& al, OperatorData& od) {
+  WF_TRY(od.xlam64.ensure(al, (size_t)od.g.xlamlen * 8));
+  WF_TRY(od.xlam32.ensure(al, (size_t)od.g.xlamlen * 4));
+  return {};
+}
+
+Status build_xlam(OperatorData& od, hipStream_t s) {
+  WF_HIP(launch_xlam_rows(od.g.n, od.lam64.as<double>(), od.xlam64.as<double>(),
+                          od.xlam32.as<float>(), s));
+  return {};
 }
 
 SolveWork::~SolveWork() {
@@ -249,7 +262,8 @@ template <typename T> static Seg<T> seg_x_main(cplx<T>* spec, const Grid& g, int
   s.n_outer = g.n;
   s.n_btiles = (int)(h / tb);
   s.n_out = g.n;
-  s.lam_outer_signed = 1;
+  s.lam_y_outer = 1;
+  s.lam_kz = -1;
   return s;
 }
 template <typename T> static Seg<T> seg_x_nyq(cplx<T>* nyq, const Grid& g, int tb) {
@@ -262,8 +276,8 @@ template <typename T> static Seg<T> seg_x_nyq(cplx<T>* nyq, const Grid& g, int t
   s.n_outer = 1;
   s.n_btiles = g.n / tb;
   s.n_out = g.n;
-  s.lam_batch_signed = 1;
-  s.lam_const = (g.n / 2) * (g.n / 2);
+  s.lam_y_outer = 0;
+  s.lam_kz = g.n / 2;
   return s;
 }
 
@@ -272,8 +286,8 @@ template <typename T> static const cplx<T>* tw_of(const OperatorData& od) {
   else return od.tw32.as<cplx<T>>();
 }
 template <typename T> static const T* lam_of(const OperatorData& od) {
-  if constexpr (sizeof(T) == 8) return od.lam64.as<T>();
-  else return od.lam32.as<T>();
+  if constexpr (sizeof(T) == 8) return od.xlam64.as<T>();
+  else return od.xlam32.as<T>();
 }
 template <typename T> static const T* w_of(const OperatorData& od) {
   if constexpr (sizeof(T) == 8) return od.w64.as<T>();
@@ -329,7 +343,8 @@ Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T
     WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, spec, false, st, skip), nrhs, s));
   }
   {
-    ProfScope ps(od.prof, kbase + 2, 2 * sb, s);
+    // spectrum in and out, one Lambda value per element
+    ProfScope ps(od.prof, kbase + 2, 2.5 * sb, s);
     WF_HIP(launch_strided<T>(g.n, SM_FWD_LAM_INV, str_args<T>(od, spec, true, st, skip), nrhs, s));
   }
   {

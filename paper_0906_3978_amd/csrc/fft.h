@@ -25,22 +25,26 @@ template <int... Rs> struct Radices {
 
 // Forward plans; the inverse runs the radices in reverse order so that the
 // last forward stage and the first inverse stage touch the same elements.
+// Every plan ends with an even radix (the x pass relies on it: the moduli
+// |m| a thread holds in that stage pair up, see xlam_rows).
 template <int N> struct Plan;
 template <> struct Plan<8> : Radices<8> {};
-template <> struct Plan<12> : Radices<4, 3> {};
+template <> struct Plan<12> : Radices<3, 4> {};
 template <> struct Plan<16> : Radices<4, 4> {};
-template <> struct Plan<24> : Radices<8, 3> {};
+template <> struct Plan<24> : Radices<3, 8> {};
 template <> struct Plan<32> : Radices<8, 4> {};
-template <> struct Plan<48> : Radices<4, 4, 3> {};
+template <> struct Plan<48> : Radices<3, 4, 4> {};
 template <> struct Plan<64> : Radices<8, 8> {};
-template <> struct Plan<96> : Radices<8, 4, 3> {};
+template <> struct Plan<96> : Radices<3, 8, 4> {};
 template <> struct Plan<128> : Radices<8, 4, 4> {};
-template <> struct Plan<192> : Radices<8, 8, 3> {};
+template <> struct Plan<192> : Radices<3, 8, 8> {};
 template <> struct Plan<256> : Radices<8, 8, 4> {};
-template <> struct Plan<384> : Radices<8, 4, 4, 3> {};
+template <> struct Plan<384> : Radices<3, 8, 4, 4> {};
 template <> struct Plan<512> : Radices<8, 8, 8> {};
-template <> struct Plan<768> : Radices<8, 8, 4, 3> {};
+template <> struct Plan<768> : Radices<3, 8, 8, 4> {};
 template <> struct Plan<1024> : Radices<8, 8, 4, 4> {};
+
+template <int N> constexpr int last_radix() { return Plan<N>::r[Plan<N>::len - 1]; }
 
 template <int N> constexpr int plan_radix(int dir, int i) {
   return dir < 0 ? Plan<N>::r[i] : Plan<N>::r[Plan<N>::len - 1 - i];

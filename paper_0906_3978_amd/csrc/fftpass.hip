@@ -12,6 +12,8 @@
 // Global memory is moved in 16-byte vectors, all loads of a thread issued
 // before their first use.  Block partials of the reductions are summed in a
 // fixed order by a one-block finalize kernel per right-hand side.
+#include <algorithm>
+
 #include "fft.h"
 #include "launch.h"
 
@@ -382,25 +384,51 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   }
   load_twiddles<T, N, NT>(twl, a.tw);
   if constexpr (MODE == SM_FWD_LAM_INV) {
-    // Lambda[|m|^2] of the elements this thread holds between the forward and
-    // the inverse transform, gathered from the L2-resident table before the
-    // forward FFT so that the loads complete under it.
-    constexpr int RL = Plan<N>::r[Plan<N>::len - 1];
-    constexpr int NBF = TB * (N / RL);
+    // Lambda of the elements this thread holds between the forward and the
+    // inverse transform, read from the column's row of the x-pass table
+    // before the forward FFT so that the loads complete under it.  Row
+    // (|my|, kz) holds tuples A_t[k] = Lambda(my^2 + kz^2 + (t + k L)^2),
+    // t = 0..L, k < R/2 (L = N/R, R the last radix).  The butterfly j holds
+    // elements e = j + r L: |m| = j + r L for r < R/2, and
+    // (L - j) + (R - 1 - r) L for the others, i.e. A_j and A_(L-j) reversed.
+    constexpr int RL = last_radix<N>();
+    static_assert(RL % 2 == 0, "x pass needs an even last radix");
+    constexpr int HR = RL / 2;
+    constexpr int L = N / RL;
+    constexpr int HN = N / 2 + 1;
+    constexpr int ROW = (L + 1) * HR;
+    constexpr int NBF = TB * L;
     constexpr int PL = (NBF + NT - 1) / NT;
     T lamv[PL][RL];
-    const int mo = s.lam_outer_signed ? signed_m(outer, N) : 0;
-    const int base = mo * mo + s.lam_const;
+    const int my_o = s.lam_y_outer ? signed_m(outer, N) : 0;
 #pragma unroll
     for (int c = 0; c < PL; ++c) {
       const int bf = threadIdx.x + c * NT;
       if (NBF % NT == 0 || bf < NBF) {
-        const int b = bf % TB;
-        const int mb = s.lam_batch_signed ? signed_m(b0 + b, N) : (b0 + b);
+        const int b = bf % TB, j = bf / TB, cb = b0 + b;
+        const int my = s.lam_y_outer ? my_o : signed_m(cb, N);
+        const int kz = s.lam_kz < 0 ? cb : s.lam_kz;
+        const T* row = a.lam + (int64_t)((my < 0 ? -my : my) * HN + kz) * ROW;
+        const T* lo = row + j * HR;
+        const T* hi = row + (L - j) * HR;
+        if constexpr ((HR * sizeof(T)) % 16 == 0) {
+          constexpr int VW = 16 / sizeof(T);
 #pragma unroll
-        for (int r = 0; r < RL; ++r) {
-          const int mi = signed_m(lam_stage_index<N, TB>(bf, r), N);
-          lamv[c][r] = a.lam[base + mi * mi + mb * mb];
+          for (int v = 0; v < HR / VW; ++v) {
+            const vec16<T> x0 = *reinterpret_cast<const vec16<T>*>(lo + v * VW);
+            const vec16<T> x1 = *reinterpret_cast<const vec16<T>*>(hi + v * VW);
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+              lamv[c][v * VW + k] = x0[k];
+              lamv[c][RL - 1 - (v * VW + k)] = x1[k];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < HR; ++k) {
+            lamv[c][k] = lo[k];
+            lamv[c][RL - 1 - k] = hi[k];
+          }
         }
       }
     }
@@ -537,6 +565,33 @@ hipError_t launch_finalize(int kind, const double* partials, int nparts, int ski
 }
 
 // ---------------------------------------------------------------------------
+// x-pass Lambda rows: for every column (|my|, kz) of the half spectrum, the
+// diagonal of eq:WF at the moduli the x pass holds in its fused stage, laid
+// out so that each thread reads two contiguous tuples (see k_strided)
+// ---------------------------------------------------------------------------
+template <int N> constexpr int64_t xlam_row() {
+  return (int64_t)(N / last_radix<N>() + 1) * (last_radix<N>() / 2);
+}
+
+template <int N>
+__global__ void k_xlam_rows(const double* __restrict__ lam, double* rows64, float* rows32) {
+  constexpr int HR = last_radix<N>() / 2, L = N / last_radix<N>(), HN = N / 2 + 1;
+  constexpr int64_t ROW = xlam_row<N>();
+  const int64_t total = (int64_t)HN * HN * ROW;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t col = i / ROW;
+    const int pos = (int)(i - col * ROW);
+    const int my = (int)(col / HN), kz = (int)(col - (int64_t)my * HN);
+    const int t = pos / HR, k = pos - t * HR;
+    const int mx = t + k * L;  // <= N/2
+    const double v = lam[(int64_t)my * my + (int64_t)kz * kz + (int64_t)mx * mx];
+    rows64[i] = v;
+    rows32[i] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers (dispatch over the supported lengths)
 // ---------------------------------------------------------------------------
 #define WF_FOR_LENGTHS(X) \
@@ -553,6 +608,31 @@ bool fft_length_supported(int n, bool fp64) {
     return fp64 || n <= 512;
     default: return false;
   }
+}
+
+int64_t xlam_elems(int n) {
+  switch (n) {
+#define X(L) \
+  case L: return (int64_t)(L / 2 + 1) * (L / 2 + 1) * xlam_row<L>();
+    WF_FOR_F32(X)
+#undef X
+    default: return 0;
+  }
+}
+
+hipError_t launch_xlam_rows(int n, const double* lam, double* rows64, float* rows32,
+                            hipStream_t s) {
+  const int64_t total = xlam_elems(n);
+  if (total <= 0) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  switch (n) {
+#define X(L) \
+  case L: hipLaunchKernelGGL(k_xlam_rows<L>, dim3(blocks), dim3(256), 0, s, lam, rows64, rows32); break;
+    WF_FOR_F32(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // Strided tiles: TB = str_tb<T, N> adjacent columns, 512 threads.

@@ -101,13 +101,16 @@ struct Grid {
   int64_t spec_main = 0;  // n * n * n/2 complex
   int64_t spec_total = 0; // + n * n (Nyquist plane)
   int64_t lamlen = 0;   // 3 (n/2)^2 + 1
+  int64_t xlamlen = 0;  // elements of the x-pass Lambda rows
   void set(int n_, double box_);
 };
 
 // The operator's constant data on the device (shared by every RHS of a grid).
 struct OperatorData {
   Grid g;
-  DevBuf w64, w32, lam64, lam32, tw64, tw32;
+  DevBuf w64, w32, tw64, tw32;
+  DevBuf lam64;           // Lambda over |m|^2 (FP64)
+  DevBuf xlam64, xlam32;  // the same, expanded into the x-pass rows
   Profiler* prof = nullptr;   // optional
 };
 
@@ -126,6 +129,9 @@ struct SolveWork {
 };
 
 Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32, hipStream_t s);
+// x-pass Lambda rows: allocation, and expansion from lam64 (on stream s)
+Status alloc_xlam(const Allocator& al, OperatorData& od);
+Status build_xlam(OperatorData& od, hipStream_t s);
 Status upload(void* dst, const void* src, size_t bytes, wf_mem mem, hipStream_t s);
 Status download(void* dst, const void* src, size_t bytes, wf_mem mem, hipStream_t s);
 

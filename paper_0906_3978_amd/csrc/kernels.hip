@@ -525,7 +525,7 @@ hipError_t launch_mask(const double* w, double* w64, float* w32, int64_t m, int*
 }
 
 __global__ void k_lambda(const double* p, int64_t len, double dv, double inv_m, double* lam64,
-                         float* lam32, int* flag) {
+                         int* flag) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < len; j += stride) {
     double l = 0.0;
@@ -536,14 +536,12 @@ __global__ void k_lambda(const double* p, int64_t len, double dv, double inv_m, 
       if (!isfinite(l)) atomicOr(flag, 1);
     }
     lam64[j] = l;
-    lam32[j] = (float)l;
   }
 }
 
 hipError_t launch_lambda(const double* p, int64_t len, double dv, double inv_m, double* lam64,
-                         float* lam32, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_lambda, fill_grid(len), dim3(256), 0, s, p, len, dv, inv_m, lam64, lam32,
-                     flag);
+                         int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_lambda, fill_grid(len), dim3(256), 0, s, p, len, dv, inv_m, lam64, flag);
   return hipGetLastError();
 }
 

@@ -54,13 +54,15 @@ template <typename T> struct Seg {
   int64_t in_outer, in_axis, in_batch, in_rhs;
   int64_t out_outer, out_axis, out_batch, out_rhs;
   int32_t n_outer, n_btiles, axis_contig, n_out;
-  int32_t lam_outer_signed, lam_batch_signed, lam_const, pad;
+  // x pass: the y index of a column is the outer index (1) or the batch
+  // index (0); its kz is the batch index (lam_kz < 0) or lam_kz
+  int32_t lam_y_outer, lam_kz, pad0, pad1;
 };
 
 template <typename T> struct StrArgs {
   Seg<T> s0, s1;
   int32_t nblk0, nblk1;
-  const T* lam;
+  const T* lam;             // x pass: Lambda rows (xlam_rows layout)
   const cplx<T>* tw;
   const CgState* st;        // may be null
   int32_t skip;             // SKIP_* (needs st)
@@ -136,7 +138,12 @@ hipError_t launch_mask(const double* w, double* w64, float* w32, int64_t m, int*
                        double* partials, uint32_t* ticket, double* sumw, hipStream_t s);
 // lam[j] = (dv / p[j]) * inv_m for j >= 1, lam[0] = 0; flags non-finite or <= 0
 hipError_t launch_lambda(const double* p, int64_t len, double dv, double inv_m, double* lam64,
-                         float* lam32, int* flag, hipStream_t s);
+                         int* flag, hipStream_t s);
+// Elements of the x-pass Lambda rows of an n^3 grid, and their expansion from
+// the table over |m|^2 (FP64 and FP32 copies).
+int64_t xlam_elems(int n);
+hipError_t launch_xlam_rows(int n, const double* lam, double* rows64, float* rows32,
+                            hipStream_t s);
 // nbar = ngal / sumw; b = w > 0 ? nobs - nbar w : 0
 hipError_t launch_data_vector(const double* nobs, const double* w, const double* sumw, double ngal,
                               double* nbar_out, double* b, int64_t m, hipStream_t s);

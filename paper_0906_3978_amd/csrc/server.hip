@@ -198,7 +198,7 @@ size_t job_footprint(int n, int ss, bool mixed, int64_t n_gal) {
   g.set(n, 1.0);
   size_t f = footprint_bytes(n, ss, mixed ? WF_MIXED : WF_FP64, 1);
   f += (size_t)n_gal * 24 + (size_t)g.m * 8 /* staging */ + (size_t)g.lamlen * 8 + 64 * 1024;
-  f += 40 * 256;  // granule rounding of every buffer
+  f += 41 * 256;  // granule rounding of every buffer
   return f;
 }
 
@@ -213,7 +213,7 @@ bool wf_server::admit(const std::shared_ptr<Job>& j, Status& why) {
     WF_TRY(j->od.w64.ensure(al, (size_t)g.m * 8));
     WF_TRY(j->od.w32.ensure(al, (size_t)g.m * 4));
     WF_TRY(j->od.lam64.ensure(al, (size_t)g.lamlen * 8));
-    WF_TRY(j->od.lam32.ensure(al, (size_t)g.lamlen * 4));
+    WF_TRY(alloc_xlam(al, j->od));
     WF_TRY(j->xyz_d.ensure(al, (size_t)std::max<int64_t>(j->n_gal, 1) * 24));
     WF_TRY(j->nobs.ensure(al, (size_t)g.m * 8));
     WF_TRY(j->scal.ensure(al, 64 * 8));
@@ -250,8 +250,8 @@ bool wf_server::admit(const std::shared_ptr<Job>& j, Status& why) {
     WF_HIP(hipMemcpyAsync(j->staging.p, j->p.data(), (size_t)g.lamlen * 8, hipMemcpyHostToDevice, s));
     const double h = g.box / g.n;
     WF_HIP(launch_lambda(j->staging.as<double>(), g.lamlen, h * h * h, 1.0 / (double)g.m,
-                         j->od.lam64.as<double>(), j->od.lam32.as<float>(),
-                         reinterpret_cast<int*>(scal + 17), s));
+                         j->od.lam64.as<double>(), reinterpret_cast<int*>(scal + 17), s));
+    WF_TRY(build_xlam(j->od, s));
     if (j->n_gal > 0)
       WF_HIP(hipMemcpyAsync(j->xyz_d.p, j->xyz.data(), (size_t)j->n_gal * 24, hipMemcpyHostToDevice, s));
     // gridding, data vector, solver state
@@ -348,7 +348,8 @@ void wf_server::retire(const std::shared_ptr<Job>& j, bool ok) {
   j->od.w64.release();
   j->od.w32.release();
   j->od.lam64.release();
-  j->od.lam32.release();
+  j->od.xlam64.release();
+  j->od.xlam32.release();
   j->od.tw64.release();
   j->od.tw32.release();
   j->dw.grid.release();
@@ -402,7 +403,7 @@ void wf_server::run() {
       Status why;
       if (!admit(j, why)) {
         // not enough contiguous arena memory now: release and wait
-        for (DevBuf* b : {&j->od.w64, &j->od.w32, &j->od.lam64, &j->od.lam32, &j->od.tw64,
+        for (DevBuf* b : {&j->od.w64, &j->od.w32, &j->od.lam64, &j->od.xlam64, &j->od.xlam32, &j->od.tw64,
                           &j->od.tw32, &j->dw.grid, &j->dw.fine_spec, &j->dw.spec_y, &j->dw.spec_c,
                           &j->dw.tw_fine, &j->xyz_d, &j->nobs, &j->scal, &j->staging, &j->sw.b64,
                           &j->sw.x64, &j->sw.r64, &j->sw.p64, &j->sw.q64, &j->sw.spec64, &j->sw.x32,

@@ -77,9 +77,6 @@ Status iterate_until_done(const OperatorData& od, SolveWork& sw, Vecs<T> v, int 
 // updates for the RHS that ask for one.
 Status iterate_reliable(const OperatorData& od, SolveWork& sw, int nr, int check, hipStream_t s) {
   Vecs<float> v = v32(sw);
-  CgState* st = sw.state.as<CgState>();
-  double* parts = sw.partials.as<double>();
-  const Grid& g = od.g;
   for (;;) {
     WF_TRY(sw.pull_state(s));
     bool all = true, update = false;
@@ -411,7 +408,7 @@ size_t footprint_bytes(int n, int ss, wf_precision prec, int nrhs) {
   Grid g;
   g.set(n, 1.0);
   const double M = (double)g.m, ST = (double)g.spec_total;
-  double op = 12.0 * M + 12.0 * g.lamlen + 24.0 * n;
+  double op = 12.0 * M + 8.0 * g.lamlen + 12.0 * g.xlamlen + 24.0 * n;
   double per = 24.0 * M + 16.0 * ST;                      // b, x, r, spec64
   per += prec == WF_FP64 ? 16.0 * M : 16.0 * M + 8.0 * ST;  // p, q | 4 FP32 vectors, spec32
   const int nf = ss * n;
