@@ -215,6 +215,9 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the grid size (testing)")
     ap.add_argument("--tol", type=float, default=DEFAULT_TOL)
     ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--precond", choices=["none", "prior"], default="none",
+                    help="CG preconditioning: none (plain CG on A) or prior (the prior-split "
+                         "system C A C)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -249,7 +252,8 @@ def main():
     ctx.set_power(p_d)
     torch.cuda.synchronize()
 
-    solve_kw = dict(precision="mixed", tol=args.tol, max_iter=100000, inner_tol=args.inner_tol)
+    solve_kw = dict(precision="mixed", tol=args.tol, max_iter=100000, inner_tol=args.inner_tol,
+                    precond=args.precond)
 
     if args.profile_iters:
         ctx.set_galaxies(xyz_d)

@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define WF_ABI_VERSION 1
+#define WF_ABI_VERSION 2
 
 typedef enum {
   WF_OK = 0,
@@ -78,6 +78,22 @@ typedef enum {
                     recomputation and solution (reliable-update refinement) */
 } wf_precision;
 
+/* Preconditioning of the CG.
+ *   WF_PRECOND_NONE   plain CG on A s = b.
+ *   WF_PRECOND_PRIOR  CG on the prior-split system (C A C) y = C b, s = C y,
+ *                     with C = S^(1/2) the square root of the prior covariance
+ *                     (Sec. 3.3.1: S is diagonal in Fourier space with
+ *                     eigenvalues P/dV; C takes their square roots, the
+ *                     monopole the |m|^2 = 1 value).  Same solution A^-1 b;
+ *                     the spectrum of C A C lies within
+ *                     [.., 1 + nbar max(w) max(P/dV)] at any resolution, while
+ *                     that of A spans the whole range of dV/P.  The CG vectors
+ *                     live in the half spectrum; tol applies to
+ *                     ||C (b - A s)|| / ||C b||; rel_res_true still reports
+ *                     ||b - A s|| / ||b|| (one FP64 operator application at
+ *                     the end). */
+typedef enum { WF_PRECOND_NONE = 0, WF_PRECOND_PRIOR = 1 } wf_precond;
+
 /* Device allocator callbacks (e.g. a framework's caching allocator).  alloc
  * returns device memory of at least `bytes` on the context's device, aligned
  * to 256 bytes, or NULL. */
@@ -100,7 +116,8 @@ typedef struct wf_server wf_server;
  *               (0: no limit).
  *   check_every host convergence checks every this many iterations (0: 16).
  *               Results do not depend on it: the device stops iterating at
- *               convergence by itself. */
+ *               convergence by itself.
+ *   precond     wf_precond (the stepwise solve supports WF_PRECOND_NONE only). */
 typedef struct {
   wf_precision precision;
   double tol;
@@ -108,6 +125,7 @@ typedef struct {
   double inner_tol;
   int32_t max_outer;
   int32_t check_every;
+  int32_t precond;
 } wf_solve_opts;
 
 typedef struct {
@@ -218,14 +236,20 @@ wf_status wf_solve_batch(wf_ctx* ctx, int32_t nrhs, const double* const* xyz,
 /* ---- live kernel timing ------------------------------------------------ */
 /* Kernel classes timed by the profiler: the five sweeps of one operator
  * application and the CG vector update, in FP32 (0..5) and FP64 (6..11),
- * then the gridding kernels. */
-#define WF_PROF_KINDS 14
+ * then the gridding kernels; then the sweeps of the prior-split operator
+ * that differ from those (its y passes, z forward pass and r update count
+ * under the classes above): the direction update, the scaled x inverse pass,
+ * the z inverse pass times nbar w, and the x forward pass that finishes
+ * q = C A C p, in FP32 (14..17) and FP64 (18..21). */
+#define WF_PROF_KINDS 22
 typedef enum {
   WF_PROF_ZFWD_F32 = 0, WF_PROF_YFWD_F32, WF_PROF_XLAM_F32, WF_PROF_YINV_F32,
   WF_PROF_ZINV_F32, WF_PROF_UPDATE_F32,
   WF_PROF_ZFWD_F64, WF_PROF_YFWD_F64, WF_PROF_XLAM_F64, WF_PROF_YINV_F64,
   WF_PROF_ZINV_F64, WF_PROF_UPDATE_F64,
-  WF_PROF_DEPOSIT, WF_PROF_SUPERSAMPLE
+  WF_PROF_DEPOSIT, WF_PROF_SUPERSAMPLE,
+  WF_PROF_SDIR_F32, WF_PROF_SXINV_F32, WF_PROF_SZW_F32, WF_PROF_SXFWD_F32,
+  WF_PROF_SDIR_F64, WF_PROF_SXINV_F64, WF_PROF_SZW_F64, WF_PROF_SXFWD_F64
 } wf_prof_kind;
 
 /* Per class: active launches, summed device time (HIP events recorded on the

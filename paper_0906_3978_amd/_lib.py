@@ -22,6 +22,7 @@ STATUS_NAMES = ["WF_OK", "WF_EINVAL", "WF_ESTATE", "WF_ENOMEM", "WF_EDEVICE", "W
 WF_HOST, WF_DEVICE = 0, 1
 SCHEMES = {"ngp": 0, "cic": 1, "tsc": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
+PRECONDS = {"none": 0, "prior": 1}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -29,7 +30,8 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 class SolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
+                ("precond", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -50,10 +52,12 @@ class Request(C.Structure):
                 ("scheme", C.c_int), ("supersample", C.c_int32), ("opts", SolveOpts)]
 
 
-PROF_KINDS = 14
+PROF_KINDS = 22
 PROF_NAMES = ["zfwd_f32", "yfwd_f32", "xlam_f32", "yinv_f32", "zinv_f32", "update_f32",
               "zfwd_f64", "yfwd_f64", "xlam_f64", "yinv_f64", "zinv_f64", "update_f64",
-              "deposit", "supersample"]
+              "deposit", "supersample",
+              "sdir_f32", "sxinv_f32", "szw_f32", "sxfwd_f32",
+              "sdir_f64", "sxinv_f64", "szw_f64", "sxfwd_f64"]
 
 
 class Profile(C.Structure):
@@ -168,7 +172,10 @@ def _torch_allocator(device):
             return None
 
     def free(ptr, user):
-        torch.cuda.caching_allocator_delete(ptr)
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except AttributeError:  # interpreter shutdown: torch is already torn down
+            pass
 
     return ALLOC_FN(alloc), FREE_FN(free)
 
@@ -190,8 +197,10 @@ def _info(si):
     return Info(**si.as_dict())
 
 
-def opts(precision="fp64", tol=1e-10, max_iter=10000, inner_tol=0.0, max_outer=0, check_every=0):
-    return SolveOpts(PRECISIONS[precision], tol, max_iter, inner_tol, max_outer, check_every)
+def opts(precision="fp64", tol=1e-10, max_iter=10000, inner_tol=0.0, max_outer=0, check_every=0,
+         precond="none"):
+    return SolveOpts(PRECISIONS[precision], tol, max_iter, inner_tol, max_outer, check_every,
+                     PRECONDS[precond])
 
 
 class Context:

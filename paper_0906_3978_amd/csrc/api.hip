@@ -132,6 +132,7 @@ wf_status wf_set_grid(wf_ctx* c, int32_t n, double box) {
   if (s.ok()) {
     c->od.g.set(n, box);
     c->have_grid = c->have_mask = c->have_power = c->have_gal = c->have_rhs = false;
+    c->od.fac_ready = false;
     c->solve_active = false;
     c->dep_scheme = -1;
     s = make_twiddles(c->al, n, c->od.tw64, &c->od.tw32, c->stream);
@@ -194,6 +195,7 @@ wf_status wf_set_power(wf_ctx* c, const double* p, int64_t len, wf_mem mem) {
       WF_TRY(upload(staging.p, p, (size_t)len * 8, WF_HOST, c->stream));
       src = staging.as<double>();
     }
+    c->od.fac_ready = false;
     WF_TRY(c->od.lam64.ensure(c->al, (size_t)len * 8));
     WF_TRY(alloc_xlam(c->al, c->od));
     WF_TRY(clear_flag(c));
@@ -399,6 +401,7 @@ wf_status wf_solve(wf_ctx* c, const wf_solve_opts* opts, double* s_out, wf_mem m
   s = validate_opts(*opts);
   if (!s.ok()) return finish(c, s);
   s = set_device(c);
+  if (s.ok() && opts->precond == WF_PRECOND_PRIOR) s = ensure_split_fac(c->al, c->od, c->stream);
   if (!s.ok()) return finish(c, s);
   SolveRequest rq;
   rq.od = &c->od;
@@ -428,6 +431,8 @@ wf_status wf_solve_begin(wf_ctx* c, const wf_solve_opts* opts) {
                   "wf_solve_begin needs grid, mask, power and a data vector");
   if (!s.ok()) return finish(c, s);
   if (opts->precision != WF_FP64) return finish(c, fail(WF_EINVAL, "stepwise solves are FP64"));
+  if (opts->precond != WF_PRECOND_NONE)
+    return finish(c, fail(WF_EINVAL, "stepwise solves are not preconditioned"));
   s = validate_opts(*opts);
   if (s.ok()) s = set_device(c);
   if (s.ok()) s = fp64_begin(c->od, c->al, c->sw, c->nbar, *opts, c->stream);
@@ -510,6 +515,7 @@ wf_status wf_solve_batch(wf_ctx* c, int32_t nrhs, const double* const* xyz, cons
       return finish(c, fail(WF_EOVERFLOW, "n_gal must be < 2^24"));
   }
   s = set_device(c);
+  if (s.ok() && opts->precond == WF_PRECOND_PRIOR) s = ensure_split_fac(c->al, c->od, c->stream);
   if (!s.ok()) return finish(c, s);
   BatchInputs bi;
   bi.nrhs = nrhs;
@@ -550,7 +556,7 @@ wf_status wf_profile_read(wf_ctx* c, wf_profile* out) {
 }
 
 size_t wf_footprint_bytes(int32_t n, int32_t ss, wf_precision prec, int32_t nrhs) {
-  return footprint_bytes(n, ss, prec, nrhs);
+  return std::max(footprint_bytes(n, ss, prec, nrhs, false), footprint_bytes(n, ss, prec, nrhs, true));
 }
 
 }  // extern "C"

@@ -55,6 +55,7 @@ struct CgState {
   int32_t max_updates;
   int32_t pending;   // 1: x still lacks alpha p of the last iteration (applied by the next
                      // z pass, a reliable-update fold or a flush)
+  double onorm;      // prior-split solves: ||b|| of the original system (bnorm is ||C b||)
 };
 
 enum : int32_t {

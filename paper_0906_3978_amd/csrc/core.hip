@@ -138,24 +138,33 @@ SolveWork::~SolveWork() {
   if (st_host) (void)hipHostFree(st_host);
 }
 
-Status SolveWork::ensure(const Allocator& al, const Grid& g, int nr, bool fp64_cg, bool mixed) {
+Status SolveWork::ensure(const Allocator& al, const Grid& g, int nr, bool fp64_cg, bool mixed,
+                         bool split_) {
   nrhs = nr;
+  split = split_;
+  vlen = split ? 2 * g.spec_total : g.m;
   const size_t m = (size_t)g.m * nr;
+  const size_t v = (size_t)vlen * nr;
   const size_t sp = (size_t)g.spec_total * nr;
   WF_TRY(b64.ensure(al, m * 8));
-  WF_TRY(x64.ensure(al, m * 8));
-  WF_TRY(r64.ensure(al, m * 8));
+  WF_TRY(x64.ensure(al, v * 8));
+  WF_TRY(r64.ensure(al, v * 8));
   WF_TRY(spec64.ensure(al, sp * 16));
   if (fp64_cg) {
-    WF_TRY(p64.ensure(al, m * 8));
-    WF_TRY(q64.ensure(al, m * 8));
+    WF_TRY(p64.ensure(al, v * 8));
+    WF_TRY(q64.ensure(al, v * 8));
   }
   if (mixed) {
-    WF_TRY(x32.ensure(al, m * 4));
-    WF_TRY(r32.ensure(al, m * 4));
-    WF_TRY(p32.ensure(al, m * 4));
-    WF_TRY(q32.ensure(al, m * 4));
+    WF_TRY(x32.ensure(al, v * 4));
+    WF_TRY(r32.ensure(al, v * 4));
+    WF_TRY(p32.ensure(al, v * 4));
+    WF_TRY(q32.ensure(al, v * 4));
     WF_TRY(spec32.ensure(al, sp * 8));
+  }
+  if (split) {
+    WF_TRY(bh64.ensure(al, v * 8));
+    WF_TRY(u64.ensure(al, m * 8));
+    if (mixed) WF_TRY(u32.ensure(al, m * 4));
   }
   // partials: enough for the largest grid of any reduction kernel per RHS
   const int64_t zblocks = g.nrows / 2;  // upper bound of z-pass blocks (NB >= 1)
@@ -391,6 +400,188 @@ template Status operator_passes<double>(const OperatorData&, int, const double*,
                                         cplx<double>*, int, double*, const double*, const double*,
                                         CgState*, double*, int, int, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// prior-split operator (C A C) on half-spectrum vectors
+// ---------------------------------------------------------------------------
+Status alloc_split_fac(const Allocator& al, OperatorData& od) {
+  const int64_t len = split_fac_elems(od.g.n);
+  WF_TRY(od.fac64.ensure(al, (size_t)len * 8));
+  WF_TRY(od.fac32.ensure(al, (size_t)len * 4));
+  return {};
+}
+
+Status build_split_fac(OperatorData& od, hipStream_t s) {
+  WF_HIP(launch_split_fac(od.g.n, od.lam64.as<double>(), (double)od.g.m, od.fac64.as<double>(),
+                          od.fac32.as<float>(), s));
+  od.fac_ready = true;
+  return {};
+}
+
+Status ensure_split_fac(const Allocator& al, OperatorData& od, hipStream_t s) {
+  if (od.fac_ready) return {};
+  WF_TRY(alloc_split_fac(al, od));
+  return build_split_fac(od, s);
+}
+
+template <typename T> static const T* fac_of(const OperatorData& od) {
+  if constexpr (sizeof(T) == 8) return od.fac64.as<T>();
+  else return od.fac32.as<T>();
+}
+
+// x pass from `in` to `out` (both half spectra), aux and b at out's positions
+template <typename T>
+static StrArgs<T> split_x_args(const OperatorData& od, const cplx<T>* in, cplx<T>* out,
+                               const cplx<T>* aux, const cplx<double>* bvec, const CgState* st,
+                               int skip, double* partials) {
+  const Grid& g = od.g;
+  const int tb = strided_tb(g.n, sizeof(T) == 8);
+  StrArgs<T> a{};
+  a.s0 = seg_x_main<T>(out, g, tb);
+  a.s1 = seg_x_nyq<T>(out + g.spec_main, g, tb);
+  a.s0.in = in;
+  a.s1.in = in + g.spec_main;
+  a.s0.aux = aux;
+  a.s1.aux = aux ? aux + g.spec_main : nullptr;
+  a.s0.bvec = bvec;
+  a.s1.bvec = bvec ? bvec + g.spec_main : nullptr;
+  a.nblk0 = a.s0.n_outer * a.s0.n_btiles;
+  a.nblk1 = a.s1.n_outer * a.s1.n_btiles;
+  a.tw = tw_of<T>(od);
+  a.st = skip != SKIP_NONE ? st : nullptr;
+  a.skip = skip;
+  a.fac = fac_of<T>(od);
+  a.in_scale = 1.0 / (double)g.m;
+  a.partials = partials;
+  return a;
+}
+
+template <typename T>
+Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* work, T* u, T* out,
+                    const double* bh, CgState* st, double* partials, int nrhs, int skip,
+                    hipStream_t s) {
+  const Grid& g = od.g;
+  const bool f64 = sizeof(T) == 8;
+  const double vb = (double)sizeof(T) * g.m * nrhs;
+  const double sb = 2.0 * sizeof(T) * g.spec_total * nrhs;
+  const cplx<T>* pc = reinterpret_cast<const cplx<T>*>(pin);
+  {
+    // p in, scaled and transformed along x into the work spectrum
+    ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 2 * sb, s);
+    WF_HIP(launch_strided<T>(g.n, SM_INV_SCALE,
+                             split_x_args<T>(od, pc, work, nullptr, nullptr, st, skip, nullptr),
+                             nrhs, s));
+  }
+  {
+    ProfScope ps(od.prof, f64 ? WF_PROF_YINV_F64 : WF_PROF_YINV_F32, 2 * sb, s);
+    WF_HIP(launch_strided<T>(g.n, SM_INV, str_args<T>(od, work, false, st, skip), nrhs, s));
+  }
+  {
+    ZinvArgs<T> zi{};
+    zi.in_main = work;
+    zi.in_nyq = work + g.spec_main;
+    zi.rhs_main = g.spec_total;
+    zi.rhs_nyq = g.spec_total;
+    zi.out = u;
+    zi.rhs_out = g.m;
+    zi.w = w_of<T>(od);
+    zi.scale = 1.0;
+    zi.tw = tw_of<T>(od);
+    zi.st = st;
+    zi.skip = skip;
+    // spectrum in, w in (once), real field out
+    ProfScope ps(od.prof, f64 ? WF_PROF_SZW_F64 : WF_PROF_SZW_F32,
+                 sb / 2 + vb + (double)sizeof(T) * g.m, s);
+    WF_HIP(launch_zinv<T>(g.n, ZOUT_W, zi, g.nrows, nrhs, s));
+  }
+  {
+    ZfwdArgs<T> zf{};
+    zf.in = u;
+    zf.out_main = work;
+    zf.out_nyq = work + g.spec_main;
+    zf.nkz_out = g.n / 2;
+    zf.rhs_in = g.m;
+    zf.rhs_main = g.spec_total;
+    zf.rhs_nyq = g.spec_total;
+    zf.tw = tw_of<T>(od);
+    zf.st = skip != SKIP_NONE ? st : nullptr;
+    zf.skip = skip;
+    ProfScope ps(od.prof, f64 ? WF_PROF_ZFWD_F64 : WF_PROF_ZFWD_F32, vb + sb / 2, s);
+    WF_HIP(launch_zfwd<T>(g.n, ZIN_REAL, zf, g.nrows, nrhs, s));
+  }
+  {
+    ProfScope ps(od.prof, f64 ? WF_PROF_YFWD_F64 : WF_PROF_YFWD_F32, 2 * sb, s);
+    WF_HIP(launch_strided<T>(g.n, SM_FWD, str_args<T>(od, work, false, st, skip), nrhs, s));
+  }
+  const StrArgs<T> xa = split_x_args<T>(od, work, reinterpret_cast<cplx<T>*>(out), pc,
+                                        reinterpret_cast<const cplx<double>*>(bh), st, skip,
+                                        partials);
+  {
+    // work spectrum in, result out; CGQ also reads p, RES y and b (FP64)
+    double xb = sb;
+    if (mode == SM_FWD_CGQ) xb += sb;
+    if (mode == SM_FWD_RES) xb += 2 * sb;
+    ProfScope ps(od.prof, f64 ? WF_PROF_SXFWD_F64 : WF_PROF_SXFWD_F32, xb, s);
+    WF_HIP(launch_strided<T>(g.n, mode, xa, nrhs, s));
+  }
+  if (mode == SM_FWD_CGQ || mode == SM_FWD_RES)
+    WF_HIP(launch_finalize(mode == SM_FWD_CGQ ? FIN_PQ : FIN_RES, partials, xa.nblk0 + xa.nblk1,
+                           skip, st, nrhs, s));
+  return {};
+}
+template Status split_passes<float>(const OperatorData&, int, const float*, cplx<float>*, float*,
+                                    float*, const double*, CgState*, double*, int, int,
+                                    hipStream_t);
+template Status split_passes<double>(const OperatorData&, int, const double*, cplx<double>*,
+                                     double*, double*, const double*, CgState*, double*, int, int,
+                                     hipStream_t);
+
+// b_hat = c sqrt(D) F b (FP64, one RHS after another share the launches)
+Status split_rhs(const OperatorData& od, const double* b, cplx<double>* work, double* bh,
+                 int nrhs, hipStream_t s) {
+  const Grid& g = od.g;
+  ZfwdArgs<double> zf{};
+  zf.in = b;
+  zf.out_main = work;
+  zf.out_nyq = work + g.spec_main;
+  zf.nkz_out = g.n / 2;
+  zf.rhs_in = g.m;
+  zf.rhs_main = g.spec_total;
+  zf.rhs_nyq = g.spec_total;
+  zf.tw = tw_of<double>(od);
+  WF_HIP(launch_zfwd<double>(g.n, ZIN_REAL, zf, g.nrows, nrhs, s));
+  WF_HIP(launch_strided<double>(g.n, SM_FWD, str_args<double>(od, work, false, nullptr, SKIP_NONE),
+                                nrhs, s));
+  WF_HIP(launch_strided<double>(g.n, SM_FWD_SCALE,
+                                split_x_args<double>(od, work, reinterpret_cast<cplx<double>*>(bh),
+                                                     nullptr, nullptr, nullptr, SKIP_NONE, nullptr),
+                                nrhs, s));
+  return {};
+}
+
+// s = C y from the half-spectrum y (FP64): scaled x inverse, y inverse, z to real
+Status split_solution(const OperatorData& od, const double* yh, cplx<double>* work, double* s_out,
+                      int nrhs, hipStream_t s) {
+  const Grid& g = od.g;
+  WF_HIP(launch_strided<double>(
+      g.n, SM_INV_SCALE,
+      split_x_args<double>(od, reinterpret_cast<const cplx<double>*>(yh), work, nullptr, nullptr,
+                           nullptr, SKIP_NONE, nullptr),
+      nrhs, s));
+  WF_HIP(launch_strided<double>(g.n, SM_INV, str_args<double>(od, work, false, nullptr, SKIP_NONE),
+                                nrhs, s));
+  ZinvArgs<double> zi{};
+  zi.in_main = work;
+  zi.in_nyq = work + g.spec_main;
+  zi.rhs_main = g.spec_total;
+  zi.rhs_nyq = g.spec_total;
+  zi.out = s_out;
+  zi.rhs_out = g.m;
+  zi.scale = 1.0;
+  zi.tw = tw_of<double>(od);
+  WF_HIP(launch_zinv<double>(g.n, ZOUT_REAL, zi, g.nrows, nrhs, s));
+  return {};
+}
+
 template <typename T>
 Status forward_passes(const OperatorData& od, const T* in, cplx<T>* spec, hipStream_t s) {
   const Grid& g = od.g;
@@ -441,7 +632,10 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
                 8.0 * mf + 2 * 16.0 * nf * nf * h + 2 * 16.0 * nf * n * h + 16.0 * g.spec_total * 5 +
                     8.0 * g.m,
                 s);
-  if (dw.tw_fine.bytes < (size_t)nf * 16) WF_TRY(make_twiddles(al, nf, dw.tw_fine, nullptr, s));
+  if (dw.tw_fine_n != nf) {
+    WF_TRY(make_twiddles(al, nf, dw.tw_fine, nullptr, s));
+    dw.tw_fine_n = nf;
+  }
   const int64_t fine_spec = (int64_t)nf * nf * h;
   WF_TRY(dw.fine_spec.ensure(al, (size_t)fine_spec * 16));
   auto* fs = dw.fine_spec.as<double2>();
@@ -516,7 +710,10 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
   return {};
 }
 
-double model_bytes_iteration(bool fp64) { return fp64 ? 152.0 : 76.0; }
-double model_bytes_residual() { return 104.0; }
+double model_bytes_iteration(bool fp64, bool split) {
+  if (split) return fp64 ? 176.0 : 88.0;
+  return fp64 ? 152.0 : 76.0;
+}
+double model_bytes_residual(bool split) { return split ? 120.0 : 104.0; }
 
 }  // namespace wf

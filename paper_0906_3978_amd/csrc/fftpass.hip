@@ -271,6 +271,10 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
       const T sc = (T)a.scale;
       st16(out + i0, re * sc);
       st16(out + i1, imv * sc);
+    } else if constexpr (MODE == ZOUT_W) {
+      const R w0 = ld16(a.w + i0), w1 = ld16(a.w + i1);
+      st16(out + i0, (nbar * w0) * re);
+      st16(out + i1, (nbar * w1) * imv);
     } else if constexpr (MODE == ZOUT_CGQ || MODE == ZOUT_APPLY) {
       const T* p = a.aux + rhs * a.rhs_aux;
       const R p0 = ld16(p + i0), p1 = ld16(p + i1);
@@ -306,6 +310,48 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
 // ---------------------------------------------------------------------------
 // strided passes (y or x axis)
 // ---------------------------------------------------------------------------
+// Prior-split factor c of the x-pass element at x index i of column cb
+// (Seg fields give the column's |my| and kz); flags the monopole.
+template <typename T, int N>
+__device__ __forceinline__ T split_c(const T* __restrict__ fac, const Seg<T>& s, int outer, int cb,
+                                     int i, int& kz, bool& dc) {
+  constexpr int H = N / 2 + 1;
+  int my = s.lam_y_outer ? signed_m(outer, N) : signed_m(cb, N);
+  my = my < 0 ? -my : my;
+  kz = s.lam_kz < 0 ? cb : s.lam_kz;
+  int mx = signed_m(i, N);
+  mx = mx < 0 ? -mx : mx;
+  dc = (my | mx | kz) == 0;
+  return fac[((int64_t)my * H + mx) * H + kz];
+}
+// sqrt(D) of a kz plane (D = 1 on kz = 0 and kz = N/2, else 2)
+template <typename T, int N> __device__ __forceinline__ T sqrt_d(int kz) {
+  return (kz == 0 || kz == N / 2) ? T(1) : T(1.41421356237309504880168872420969808);
+}
+
+// Output value of the split modes from the forward-transformed element v.
+template <typename T, int N, int MODE>
+__device__ __forceinline__ cplx<T> split_out(const StrArgs<T>& a, const Seg<T>& s, int outer, int cb,
+                                            int i, cplx<T> v, const cplx<T>* auxp,
+                                            const cplx<double>* bp, double& acc) {
+  int kz;
+  bool dc;
+  const T f = split_c<T, N>(a.fac, s, outer, cb, i, kz, dc) * sqrt_d<T, N>(kz);
+  cplx<T> o = {f * v.x, f * v.y};
+  if constexpr (MODE == SM_FWD_CGQ) {
+    const cplx<T> pv = *auxp;
+    if (!dc) o = cadd(o, pv);
+    acc += (double)pv.x * (double)o.x + (double)pv.y * (double)o.y;
+  } else if constexpr (MODE == SM_FWD_RES) {
+    const cplx<T> yv = *auxp;
+    if (!dc) o = cadd(o, yv);
+    const cplx<double> bv = *bp;
+    o = {(T)(bv.x - (double)o.x), (T)(bv.y - (double)o.y)};
+    acc += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+  }
+  return o;
+}
+
 template <typename T, int N, int MODE, int TB, int NTS>
 __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   constexpr int NT = NTS;
@@ -319,6 +365,9 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   constexpr int PER = (ITEMS + NT - 1) / NT;
   __shared__ __align__(16) V lds[TB * N];
   __shared__ V twl[N];
+  constexpr bool SPLIT_OUT = MODE == SM_FWD_SCALE || MODE == SM_FWD_CGQ || MODE == SM_FWD_RES;
+  constexpr bool REDUCE = MODE == SM_FWD_CGQ || MODE == SM_FWD_RES;
+  __shared__ double red[REDUCE ? NT / 64 : 1];
   const int rhs = blockIdx.y;
   if (a.st && skip_rhs(a.st + rhs, a.skip)) return;
   int blk = blockIdx.x;
@@ -344,12 +393,34 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
 #pragma unroll
       for (int c = 0; c < PER; ++c) {
         const int q = threadIdx.x + c * NT;
-        if (ITEMS % NT == 0 || q < ITEMS) *reinterpret_cast<R*>(lds + q * CW) = buf[c];
+        if (ITEMS % NT == 0 || q < ITEMS) {
+          if constexpr (MODE == SM_INV_SCALE) {
+            const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+              int kz;
+              bool dc;
+              const T f = split_c<T, N>(a.fac, s, outer, b0 + b + j, i, kz, dc) *
+                          ((T)a.in_scale / sqrt_d<T, N>(kz));
+              buf[c][2 * j] *= f;
+              buf[c][2 * j + 1] *= f;
+            }
+          }
+          *reinterpret_cast<R*>(lds + q * CW) = buf[c];
+        }
       }
     } else {
       for (int e = threadIdx.x; e < TB * N; e += NT) {
         const int b = e % TB, i = e / TB;
-        lds[e] = in[i * s.in_axis + b];
+        V v = in[i * s.in_axis + b];
+        if constexpr (MODE == SM_INV_SCALE) {
+          int kz;
+          bool dc;
+          const T f = split_c<T, N>(a.fac, s, outer, b0 + b, i, kz, dc) *
+                      ((T)a.in_scale / sqrt_d<T, N>(kz));
+          v = {v.x * f, v.y * f};
+        }
+        lds[e] = v;
       }
     }
   } else {
@@ -436,7 +507,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
     fft_tile_diag<T, N, TB, NT>(lds, twl, lamv);
   } else {
     __syncthreads();
-    if constexpr (MODE == SM_INV) fft_tile<T, N, TB, NT, true, +1>(lds, twl);
+    if constexpr (MODE == SM_INV || MODE == SM_INV_SCALE) fft_tile<T, N, TB, NT, true, +1>(lds, twl);
     else fft_tile<T, N, TB, NT, true, -1>(lds, twl);
   }
 
@@ -448,6 +519,44 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
       V v = {T(0), T(0)};
       if (o != h) v = lds[(o < h ? o : o + (N - no)) * TB + b];
       out[o * s.out_axis + b] = v;
+    }
+  } else if constexpr (SPLIT_OUT) {
+    // x-pass segments only (the batch is contiguous)
+    double acc = 0.0;
+    const int64_t ob = rhs * s.out_rhs + outer * s.out_outer + b0 * s.out_batch;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int c = 0; c < PER; ++c) {
+        const int q = threadIdx.x + c * NT;
+        if (ITEMS % NT == 0 || q < ITEMS) {
+          const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+          const int64_t off = ob + i * s.out_axis + b;
+          const R v = *reinterpret_cast<const R*>(lds + q * CW);
+          R o;
+#pragma unroll
+          for (int j = 0; j < CW; ++j) {
+            const cplx<T> r = split_out<T, N, MODE>(
+                a, s, outer, b0 + b + j, i, V{v[2 * j], v[2 * j + 1]},
+                REDUCE ? s.aux + off + j : nullptr,
+                MODE == SM_FWD_RES ? s.bvec + off + j : nullptr, acc);
+            o[2 * j] = r.x;
+            o[2 * j + 1] = r.y;
+          }
+          st16x<NTA>(reinterpret_cast<T*>(s.out + off), o);
+        }
+      }
+    } else {
+      for (int e = threadIdx.x; e < TB * N; e += NT) {
+        const int b = e % TB, i = e / TB;
+        const int64_t off = ob + i * s.out_axis + b;
+        s.out[off] = split_out<T, N, MODE>(a, s, outer, b0 + b, i, lds[e],
+                                           REDUCE ? s.aux + off : nullptr,
+                                           MODE == SM_FWD_RES ? s.bvec + off : nullptr, acc);
+      }
+    }
+    if constexpr (REDUCE) {
+      const double part = block_sum(acc, red);
+      if (threadIdx.x == 0) a.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = part;
     }
   } else if (!s.axis_contig) {
     if constexpr (VEC) {
@@ -610,6 +719,37 @@ bool fft_length_supported(int n, bool fp64) {
   }
 }
 
+int64_t split_fac_elems(int n) {
+  const int64_t h = n / 2 + 1;
+  return (n >= 8 && n % 2 == 0) ? h * h * h : 0;
+}
+
+__global__ void k_split_fac(const double* __restrict__ lam, int h, double m_cells, double* fac64,
+                            float* fac32) {
+  const int64_t total = (int64_t)h * h * h;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int my = (int)(i / ((int64_t)h * h));
+    const int mx = (int)((i / h) % h);
+    const int kz = (int)(i % h);
+    int64_t j = (int64_t)my * my + (int64_t)mx * mx + (int64_t)kz * kz;
+    if (j == 0) j = 1;  // the monopole takes the |m|^2 = 1 value
+    const double c = 1.0 / sqrt(lam[j] * m_cells);
+    fac64[i] = c;
+    fac32[i] = (float)c;
+  }
+}
+
+hipError_t launch_split_fac(int n, const double* lam, double m_cells, double* fac64, float* fac32,
+                            hipStream_t s) {
+  const int64_t total = split_fac_elems(n);
+  if (total <= 0) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_split_fac, dim3(blocks), dim3(256), 0, s, lam, n / 2 + 1, m_cells, fac64,
+                     fac32);
+  return hipGetLastError();
+}
+
 int64_t xlam_elems(int n) {
   switch (n) {
 #define X(L) \
@@ -692,6 +832,7 @@ static hipError_t zinv_n(int mode, const ZinvArgs<T>& a, int64_t nrows, int nrhs
       }
       return hipErrorInvalidValue;
     case ZOUT_APPLY: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_APPLY>), grid, dim3(NT), 0, s, a); break;
+    case ZOUT_W: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_W>), grid, dim3(NT), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -709,6 +850,24 @@ static hipError_t strided_v(int mode, const StrArgs<T>& a, int nrhs, hipStream_t
     case SM_FWD_CROP:
       hipLaunchKernelGGL((k_strided<T, N, SM_FWD_CROP, TBV, NTV>), grid, dim3(NTV), 0, s, a);
       break;
+    case SM_INV_SCALE:
+    case SM_FWD_SCALE:
+    case SM_FWD_CGQ:
+    case SM_FWD_RES:
+      if constexpr (N <= 512) {
+        if (mode == SM_INV_SCALE)
+          hipLaunchKernelGGL((k_strided<T, N, SM_INV_SCALE, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+        else if (mode == SM_FWD_SCALE)
+          hipLaunchKernelGGL((k_strided<T, N, SM_FWD_SCALE, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+        else if (mode == SM_FWD_CGQ)
+          hipLaunchKernelGGL((k_strided<T, N, SM_FWD_CGQ, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+        else if constexpr (sizeof(T) == 8)
+          hipLaunchKernelGGL((k_strided<T, N, SM_FWD_RES, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+        else
+          return hipErrorInvalidValue;
+        break;
+      }
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

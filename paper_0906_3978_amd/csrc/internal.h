@@ -111,24 +111,50 @@ struct OperatorData {
   DevBuf w64, w32, tw64, tw32;
   DevBuf lam64;           // Lambda over |m|^2 (FP64)
   DevBuf xlam64, xlam32;  // the same, expanded into the x-pass rows
+  DevBuf fac64, fac32;    // prior-split factor c over (|my|, |mx|, kz), built on demand
+  bool fac_ready = false;
   Profiler* prof = nullptr;   // optional
 };
 
 // Workspace of solves on a grid for `nrhs` right-hand sides.
 struct SolveWork {
   int nrhs = 0;
+  // prior-split solves: x, r, p, q hold half spectra (vlen = 2 spec_total
+  // elements per RHS, complex interleaved) and x64 receives the real solution
+  // (n^3 per RHS) at the end; otherwise vlen = n^3
+  bool split = false;
+  int64_t vlen = 0;
   DevBuf b64, x64, r64, p64, q64, spec64;
   DevBuf x32, r32, p32, q32, spec32;
+  DevBuf bh64, u64, u32;  // split: C b (half spectrum), real scratch fields
   DevBuf state, partials;
   CgState* st_host = nullptr;   // pinned mirror of the state array
   int st_cap = 0;
   ~SolveWork();
   // b, x, r and the FP64 spectrum always; p, q (FP64 CG); the FP32 set (mixed)
-  Status ensure(const Allocator& al, const Grid& g, int nrhs, bool fp64_cg, bool mixed);
+  Status ensure(const Allocator& al, const Grid& g, int nrhs, bool fp64_cg, bool mixed,
+                bool split = false);
   Status pull_state(hipStream_t s);
 };
 
 Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32, hipStream_t s);
+// Prior-split operator (C A C) on half-spectrum vectors (stride spec_total
+// complex per RHS).  ensure_split_fac builds c once per power spectrum.
+// split_passes: q = C A C p (mode SM_FWD_CGQ, with p.q and FIN_PQ) or
+// r = b_hat - C A C y (SM_FWD_RES, FP64, with ||r||^2 and FIN_RES); `u` is a
+// real scratch field per RHS.  split_rhs: b_hat = C b.  split_solution:
+// s = C y into real fields.
+Status ensure_split_fac(const Allocator& al, OperatorData& od, hipStream_t s);
+Status alloc_split_fac(const Allocator& al, OperatorData& od);
+Status build_split_fac(OperatorData& od, hipStream_t s);
+template <typename T>
+Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* work, T* u, T* out,
+                    const double* bh, CgState* st, double* partials, int nrhs, int skip,
+                    hipStream_t s);
+Status split_rhs(const OperatorData& od, const double* b, cplx<double>* work, double* bh,
+                 int nrhs, hipStream_t s);
+Status split_solution(const OperatorData& od, const double* yh, cplx<double>* work, double* s_out,
+                      int nrhs, hipStream_t s);
 // x-pass Lambda rows: allocation, and expansion from lam64 (on stream s)
 Status alloc_xlam(const Allocator& al, OperatorData& od);
 Status build_xlam(OperatorData& od, hipStream_t s);
@@ -149,6 +175,7 @@ Status forward_passes(const OperatorData& od, const T* in, cplx<T>* spec, hipStr
 // Gridding of one catalogue into n_obs (n^3 doubles) -- Sec. 3.1.2.
 struct DepositWork {
   DevBuf grid, fine_spec, spec_y, spec_c, tw_fine, flag;
+  int tw_fine_n = 0;  // length tw_fine holds the twiddles of
 };
 Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
                    const double* xyz_dev, int64_t ngal, int scheme, int supersample,
@@ -156,7 +183,7 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
 
 // Algorithmic HBM bytes of one CG iteration (model of the five sweeps plus
 // the vector update) and of one FP64 residual recomputation, per cell.
-double model_bytes_iteration(bool fp64);
-double model_bytes_residual();
+double model_bytes_iteration(bool fp64, bool split = false);
+double model_bytes_residual(bool split = false);
 
 }  // namespace wf

@@ -10,7 +10,7 @@ namespace wf {
 
 // ---- z-axis passes (contiguous rows, real <-> half spectrum) --------------
 enum ZinMode : int { ZIN_REAL = 0, ZIN_CGP = 1, ZIN_I64 = 2 };
-enum ZoutMode : int { ZOUT_REAL = 0, ZOUT_CGQ = 1, ZOUT_RES = 2, ZOUT_APPLY = 3 };
+enum ZoutMode : int { ZOUT_REAL = 0, ZOUT_CGQ = 1, ZOUT_RES = 2, ZOUT_APPLY = 3, ZOUT_W = 4 };
 
 template <typename T> struct ZfwdArgs {
   const T* in;              // ZIN_REAL: rows; ZIN_CGP: r
@@ -35,7 +35,7 @@ template <typename T> struct ZinvArgs {
   int64_t rhs_out;
   const T* aux;             // CGQ: p; RES: x; APPLY: v
   int64_t rhs_aux;
-  const T* w;               // mask (shared by all RHS)
+  const T* w;               // mask (shared by all RHS); W: out = nbar w * (inverse FFT)
   const double* bvec;       // RES: b
   int64_t rhs_b;
   double scale;             // REAL: output scale
@@ -46,7 +46,18 @@ template <typename T> struct ZinvArgs {
 };
 
 // ---- strided passes (y or x axis), tiles of TB neighbouring pencils -------
-enum StrMode : int { SM_FWD = 0, SM_INV = 1, SM_FWD_LAM_INV = 2, SM_FWD_CROP = 3 };
+// The x-pass modes of the prior-split operator (see split_passes) scale by the
+// split factor: INV_SCALE multiplies the input by c / (M sqrt(D)) before the
+// inverse FFT; FWD_SCALE multiplies the output by c sqrt(D); FWD_CGQ writes
+// q = [m != 0] aux + c sqrt(D) v and the block partial of aux.q; FWD_RES (FP64)
+// writes r = b - ([m != 0] aux + c sqrt(D) v) and the block partial of r.r.
+// D = 2 for 0 < kz < N/2 and 1 on the kz = 0 and kz = N/2 planes: the half
+// spectrum stores each conjugate pair once, and carrying sqrt(D) in the vectors
+// makes their plain dot products the full-spectrum inner products.
+enum StrMode : int {
+  SM_FWD = 0, SM_INV = 1, SM_FWD_LAM_INV = 2, SM_FWD_CROP = 3,
+  SM_INV_SCALE = 4, SM_FWD_SCALE = 5, SM_FWD_CGQ = 6, SM_FWD_RES = 7
+};
 
 template <typename T> struct Seg {
   const cplx<T>* in;
@@ -57,6 +68,8 @@ template <typename T> struct Seg {
   // x pass: the y index of a column is the outer index (1) or the batch
   // index (0); its kz is the batch index (lam_kz < 0) or lam_kz
   int32_t lam_y_outer, lam_kz, pad0, pad1;
+  const cplx<T>* aux;       // split CGQ / RES: vector at the output's positions
+  const cplx<double>* bvec; // split RES: b at the output's positions
 };
 
 template <typename T> struct StrArgs {
@@ -66,6 +79,9 @@ template <typename T> struct StrArgs {
   const cplx<T>* tw;
   const CgState* st;        // may be null
   int32_t skip;             // SKIP_* (needs st)
+  const T* fac;             // split modes: c over (|my|, |mx|, kz), [|my|][|mx|][kz]
+  double in_scale;          // SM_INV_SCALE: 1 / M
+  double* partials;         // SM_FWD_CGQ / SM_FWD_RES: per RHS, one per block
 };
 
 int strided_tb(int n, bool fp64);   // batch width of a strided tile
@@ -144,6 +160,19 @@ hipError_t launch_lambda(const double* p, int64_t len, double dv, double inv_m, 
 int64_t xlam_elems(int n);
 hipError_t launch_xlam_rows(int n, const double* lam, double* rows64, float* rows32,
                             hipStream_t s);
+// Prior-split factor c = Lambda^(-1/2) over (|my|, |mx|, kz) in [0, n/2]^3 from
+// the |m|^2 table (which carries 1/M), c at |m|^2 = 1 standing in for the
+// monopole; FP64 and FP32 copies.
+int64_t split_fac_elems(int n);
+hipError_t launch_split_fac(int n, const double* lam, double m_cells, double* fac64, float* fac32,
+                            hipStream_t s);
+// CG direction on flat vectors: (pending) x += alpha p; p = r + beta p (p = r first)
+template <typename T> hipError_t launch_cg_dir(T* x, T* p, const T* r, int64_t m,
+                                               int64_t rhs_stride, const CgState* st, int nrhs,
+                                               hipStream_t s);
+// onorm = ||v|| per RHS
+hipError_t launch_state_norm(const double* v, int64_t m, int64_t rhs_stride, double* partials,
+                             CgState* st, int nrhs, hipStream_t s);
 // nbar = ngal / sumw; b = w > 0 ? nobs - nbar w : 0
 hipError_t launch_data_vector(const double* nobs, const double* w, const double* sumw, double ngal,
                               double* nbar_out, double* b, int64_t m, hipStream_t s);

@@ -113,6 +113,7 @@ struct Job {
   int scheme = 0, ss = 1;
   wf_solve_opts opts{};
   bool mixed = true;
+  bool split = false;
   // device side
   OperatorData od;
   DepositWork dw;
@@ -193,12 +194,12 @@ Status validate_request(const wf_request& r) {
   return {};
 }
 
-size_t job_footprint(int n, int ss, bool mixed, int64_t n_gal) {
+size_t job_footprint(int n, int ss, bool mixed, bool split, int64_t n_gal) {
   Grid g;
   g.set(n, 1.0);
-  size_t f = footprint_bytes(n, ss, mixed ? WF_MIXED : WF_FP64, 1);
+  size_t f = footprint_bytes(n, ss, mixed ? WF_MIXED : WF_FP64, 1, split);
   f += (size_t)n_gal * 24 + (size_t)g.m * 8 /* staging */ + (size_t)g.lamlen * 8 + 64 * 1024;
-  f += 41 * 256;  // granule rounding of every buffer
+  f += 48 * 256;  // granule rounding of every buffer
   return f;
 }
 
@@ -214,11 +215,12 @@ bool wf_server::admit(const std::shared_ptr<Job>& j, Status& why) {
     WF_TRY(j->od.w32.ensure(al, (size_t)g.m * 4));
     WF_TRY(j->od.lam64.ensure(al, (size_t)g.lamlen * 8));
     WF_TRY(alloc_xlam(al, j->od));
+    if (j->split) WF_TRY(alloc_split_fac(al, j->od));
     WF_TRY(j->xyz_d.ensure(al, (size_t)std::max<int64_t>(j->n_gal, 1) * 24));
     WF_TRY(j->nobs.ensure(al, (size_t)g.m * 8));
     WF_TRY(j->scal.ensure(al, 64 * 8));
     WF_TRY(j->staging.ensure(al, std::max<size_t>((size_t)g.lamlen * 8, 4096 * 8)));
-    WF_TRY(j->sw.ensure(al, g, 1, !j->mixed, j->mixed));
+    WF_TRY(j->sw.ensure(al, g, 1, !j->mixed, j->mixed, j->split));
     const int nf = j->ss * g.n;
     WF_TRY(j->dw.grid.ensure(al, (size_t)nf * nf * nf * 8));
     if (j->ss == 2) {
@@ -227,6 +229,7 @@ bool wf_server::admit(const std::shared_ptr<Job>& j, Status& why) {
       WF_TRY(j->dw.spec_y.ensure(al, (size_t)nf * g.n * h * 16));
       WF_TRY(j->dw.spec_c.ensure(al, (size_t)g.spec_total * 16));
       WF_TRY(make_twiddles(al, nf, j->dw.tw_fine, nullptr, s));
+      j->dw.tw_fine_n = nf;
     }
     WF_TRY(make_twiddles(al, g.n, j->od.tw64, &j->od.tw32, s));
     return {};
@@ -252,6 +255,7 @@ bool wf_server::admit(const std::shared_ptr<Job>& j, Status& why) {
     WF_HIP(launch_lambda(j->staging.as<double>(), g.lamlen, h * h * h, 1.0 / (double)g.m,
                          j->od.lam64.as<double>(), reinterpret_cast<int*>(scal + 17), s));
     WF_TRY(build_xlam(j->od, s));
+    if (j->split) WF_TRY(build_split_fac(j->od, s));
     if (j->n_gal > 0)
       WF_HIP(hipMemcpyAsync(j->xyz_d.p, j->xyz.data(), (size_t)j->n_gal * 24, hipMemcpyHostToDevice, s));
     // gridding, data vector, solver state
@@ -306,8 +310,8 @@ bool wf_server::advance(const std::shared_ptr<Job>& j) {
         WF_TRY(solve_update(j->od, j->sw, 1, s));
         WF_TRY(solve_chunk(j->od, j->sw, 1, true, chunk, s));
       } else if (c.done) {
-        if (!j->mixed) {
-          WF_TRY(solve_true_residual(j->od, j->sw, 1, s));
+        if (!j->mixed || j->split) {
+          WF_TRY(solve_finish(j->od, j->sw, 1, j->mixed, s));
           j->phase = FINAL_RES;
         } else {
           j->result.resize(j->od.g.m);
@@ -325,7 +329,8 @@ bool wf_server::advance(const std::shared_ptr<Job>& j) {
       j->phase = COPYING;
     } else if (j->phase == COPYING) {
       j->t_done = Clock::now();
-      solve_infos(j->sw.st_host, 1, j->mixed, j->od.g, ms_between(j->t_start, j->t_done), &j->info);
+      solve_infos(j->sw.st_host, 1, j->mixed, j->split, j->od.g, ms_between(j->t_start, j->t_done),
+                  &j->info);
       j->phase = DONE;
       return {};
     }
@@ -350,6 +355,11 @@ void wf_server::retire(const std::shared_ptr<Job>& j, bool ok) {
   j->od.lam64.release();
   j->od.xlam64.release();
   j->od.xlam32.release();
+  j->od.fac64.release();
+  j->od.fac32.release();
+  j->sw.bh64.release();
+  j->sw.u64.release();
+  j->sw.u32.release();
   j->od.tw64.release();
   j->od.tw32.release();
   j->dw.grid.release();
@@ -362,7 +372,7 @@ void wf_server::retire(const std::shared_ptr<Job>& j, bool ok) {
   j->scal.release();
   j->staging.release();
   for (DevBuf* b : {&j->sw.b64, &j->sw.x64, &j->sw.r64, &j->sw.p64, &j->sw.q64, &j->sw.spec64,
-                    &j->sw.x32, &j->sw.r32, &j->sw.p32, &j->sw.q32, &j->sw.spec32, &j->sw.state,
+                    &j->sw.x32, &j->sw.r32, &j->sw.p32, &j->sw.q32, &j->sw.spec32, &j->sw.bh64, &j->sw.u64, &j->sw.u32, &j->sw.state,
                     &j->sw.partials})
     b->release();
   std::vector<double>().swap(j->w);
@@ -403,11 +413,11 @@ void wf_server::run() {
       Status why;
       if (!admit(j, why)) {
         // not enough contiguous arena memory now: release and wait
-        for (DevBuf* b : {&j->od.w64, &j->od.w32, &j->od.lam64, &j->od.xlam64, &j->od.xlam32, &j->od.tw64,
+        for (DevBuf* b : {&j->od.w64, &j->od.w32, &j->od.lam64, &j->od.xlam64, &j->od.xlam32, &j->od.fac64, &j->od.fac32, &j->od.tw64,
                           &j->od.tw32, &j->dw.grid, &j->dw.fine_spec, &j->dw.spec_y, &j->dw.spec_c,
                           &j->dw.tw_fine, &j->xyz_d, &j->nobs, &j->scal, &j->staging, &j->sw.b64,
                           &j->sw.x64, &j->sw.r64, &j->sw.p64, &j->sw.q64, &j->sw.spec64, &j->sw.x32,
-                          &j->sw.r32, &j->sw.p32, &j->sw.q32, &j->sw.spec32, &j->sw.state,
+                          &j->sw.r32, &j->sw.p32, &j->sw.q32, &j->sw.spec32, &j->sw.bh64, &j->sw.u64, &j->sw.u32, &j->sw.state,
                           &j->sw.partials})
           b->release();
         std::lock_guard<std::mutex> g(mu);
@@ -507,7 +517,8 @@ wf_status wf_server_submit(wf_server* s, const wf_request* r, uint64_t* ticket) 
     return v.code;
   }
   const bool mixed = r->opts.precision == WF_MIXED;
-  const size_t need = job_footprint(r->n, r->supersample, mixed, r->n_gal);
+  const bool split = r->opts.precond == WF_PRECOND_PRIOR;
+  const size_t need = job_footprint(r->n, r->supersample, mixed, split, r->n_gal);
   if (need > s->arena.size) {
     std::lock_guard<std::mutex> g(s->mu);
     s->err = "request needs " + std::to_string(need) + " bytes, the budget is " +
@@ -527,6 +538,7 @@ wf_status wf_server_submit(wf_server* s, const wf_request* r, uint64_t* ticket) 
   j->ss = r->supersample;
   j->opts = r->opts;
   j->mixed = mixed;
+  j->split = split;
   j->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -29,9 +29,11 @@ Status solve_chunk(const OperatorData& od, SolveWork& sw, int nr, bool mixed, in
                    hipStream_t s);
 // mixed: reliable update of the RHS whose state asks for one
 Status solve_update(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s);
-// FP64: ||b - A x||^2 into outer_rr
-Status solve_true_residual(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s);
-void solve_infos(const CgState* st, int nr, bool mixed, const Grid& g, double ms,
+// after the iterations: FP64 plain CG applies the pending step and puts
+// ||b - A x||^2 into outer_rr; prior-split solves (either precision) also
+// turn the half-spectrum y into s = C y in x64; plain mixed solves need nothing
+Status solve_finish(const OperatorData& od, SolveWork& sw, int nr, bool mixed, hipStream_t s);
+void solve_infos(const CgState* st, int nr, bool mixed, bool split, const Grid& g, double ms,
                  wf_solve_info* infos);
 
 // Stepwise FP64 solve of one RHS (checkpoint / resume).
@@ -56,6 +58,6 @@ Status run_batch(const OperatorData& od, const Allocator& al, DepositWork& dw,
                  const BatchInputs& bi, const wf_solve_opts& o, double* const* s_out,
                  wf_solve_info* infos, double sumw, hipStream_t s);
 
-size_t footprint_bytes(int n, int ss, wf_precision prec, int nrhs);
+size_t footprint_bytes(int n, int ss, wf_precision prec, int nrhs, bool split);
 
 }  // namespace wf

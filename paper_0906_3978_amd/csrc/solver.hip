@@ -27,6 +27,8 @@ Status validate_opts(const wf_solve_opts& o) {
   if (o.max_iter < 0) return fail(WF_EINVAL, "max_iter must be >= 0");
   if (!(o.inner_tol >= 0.0) || o.inner_tol >= 1.0) return fail(WF_EINVAL, "inner_tol must be in [0, 1)");
   if (o.max_outer < 0 || o.check_every < 0) return fail(WF_EINVAL, "max_outer and check_every must be >= 0");
+  if (o.precond != WF_PRECOND_NONE && o.precond != WF_PRECOND_PRIOR)
+    return fail(WF_EINVAL, "unknown precond");
   return {};
 }
 
@@ -60,6 +62,39 @@ Status cg_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hi
   return {};
 }
 
+// One CG iteration of the prior-split system; vectors are half spectra.
+template <typename T>
+Status split_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, T* u, int nr,
+                       hipStream_t s) {
+  CgState* st = sw.state.as<CgState>();
+  double* parts = sw.partials.as<double>();
+  const int64_t vl = sw.vlen;
+  const bool f64 = sizeof(T) == 8;
+  {
+    // r, p, x in; p, x out
+    ProfScope ps(od.prof, f64 ? WF_PROF_SDIR_F64 : WF_PROF_SDIR_F32, 5.0 * sizeof(T) * vl * nr, s);
+    WF_HIP(launch_cg_dir<T>(v.x, v.p, v.r, vl, vl, st, nr, s));
+  }
+  WF_TRY(split_passes<T>(od, SM_FWD_CGQ, v.p, v.spec, u, v.q, nullptr, st, parts, nr, SKIP_DONE,
+                         s));
+  {
+    ProfScope ps(od.prof, f64 ? WF_PROF_UPDATE_F64 : WF_PROF_UPDATE_F32, 3.0 * sizeof(T) * vl * nr,
+                 s);
+    WF_HIP(launch_cg_update<T>(v.r, v.q, vl, vl, parts, st, nr, s));
+  }
+  WF_HIP(launch_finalize(FIN_RR, parts, update_blocks(vl, f64), SKIP_DONE, st, nr, s));
+  return {};
+}
+
+template <typename T>
+Status any_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hipStream_t s) {
+  if (!sw.split) return cg_iteration<T>(od, sw, v, nr, s);
+  T* u;
+  if constexpr (sizeof(T) == 8) u = sw.u64.as<double>();
+  else u = sw.u32.as<float>();
+  return split_iteration<T>(od, sw, v, u, nr, s);
+}
+
 // Runs CG iterations in chunks of `check` until every RHS is done.
 template <typename T>
 Status iterate_until_done(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, int check,
@@ -69,7 +104,7 @@ Status iterate_until_done(const OperatorData& od, SolveWork& sw, Vecs<T> v, int 
     bool all = true;
     for (int i = 0; i < nr; ++i) all = all && sw.st_host[i].done;
     if (all) return {};
-    for (int k = 0; k < check; ++k) WF_TRY(cg_iteration<T>(od, sw, v, nr, s));
+    for (int k = 0; k < check; ++k) WF_TRY(any_iteration<T>(od, sw, v, nr, s));
   }
 }
 
@@ -89,7 +124,7 @@ Status iterate_reliable(const OperatorData& od, SolveWork& sw, int nr, int check
       continue;
     }
     if (all) return {};
-    for (int k = 0; k < check; ++k) WF_TRY(cg_iteration<float>(od, sw, v, nr, s));
+    for (int k = 0; k < check; ++k) WF_TRY(any_iteration<float>(od, sw, v, nr, s));
   }
 }
 
@@ -154,14 +189,24 @@ Status true_residual(const OperatorData& od, SolveWork& sw, double* out, int nr,
 
 Status solve_start(const OperatorData& od, SolveWork& sw, int nr, bool mixed, hipStream_t s) {
   const Grid& g = od.g;
+  CgState* st = sw.state.as<CgState>();
+  double* parts = sw.partials.as<double>();
+  const double* b = sw.b64.as<double>();
+  int64_t vl = g.m;
+  if (sw.split) {
+    if (!od.fac_ready) return fail(WF_ESTATE, "prior-split factor not built");
+    // b_hat = C b; onorm = ||b||
+    WF_TRY(split_rhs(od, b, sw.spec64.as<double2>(), sw.bh64.as<double>(), nr, s));
+    WF_HIP(launch_state_norm(b, g.m, g.m, parts, st, nr, s));
+    b = sw.bh64.as<double>();
+    vl = sw.vlen;
+  }
   if (mixed) {
-    WF_HIP(launch_rel_init(sw.x64.as<double>(), sw.r64.as<double>(), sw.b64.as<double>(),
-                           sw.x32.as<float>(), sw.r32.as<float>(), g.m, g.m,
-                           sw.partials.as<double>(), sw.state.as<CgState>(), nr, s));
+    WF_HIP(launch_rel_init(sw.x64.as<double>(), sw.r64.as<double>(), b, sw.x32.as<float>(),
+                           sw.r32.as<float>(), vl, vl, parts, st, nr, s));
   } else {
-    Vecs<double> v = v64(sw);
-    WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), g.m, g.m,
-                                  sw.partials.as<double>(), sw.state.as<CgState>(), nr, s));
+    WF_HIP(launch_cg_init<double>(sw.x64.as<double>(), sw.r64.as<double>(), b, vl, vl, parts, st,
+                                  nr, s));
   }
   return {};
 }
@@ -170,10 +215,10 @@ Status solve_chunk(const OperatorData& od, SolveWork& sw, int nr, bool mixed, in
                    hipStream_t s) {
   if (mixed) {
     Vecs<float> v = v32(sw);
-    for (int k = 0; k < iters; ++k) WF_TRY(cg_iteration<float>(od, sw, v, nr, s));
+    for (int k = 0; k < iters; ++k) WF_TRY(any_iteration<float>(od, sw, v, nr, s));
   } else {
     Vecs<double> v = v64(sw);
-    for (int k = 0; k < iters; ++k) WF_TRY(cg_iteration<double>(od, sw, v, nr, s));
+    for (int k = 0; k < iters; ++k) WF_TRY(any_iteration<double>(od, sw, v, nr, s));
   }
   return {};
 }
@@ -182,21 +227,42 @@ Status solve_update(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s
   const Grid& g = od.g;
   CgState* st = sw.state.as<CgState>();
   double* parts = sw.partials.as<double>();
-  WF_HIP(launch_rel_fold(sw.x64.as<double>(), sw.x32.as<float>(), sw.p32.as<float>(), g.m, g.m, st,
+  const int64_t vl = sw.split ? sw.vlen : g.m;
+  WF_HIP(launch_rel_fold(sw.x64.as<double>(), sw.x32.as<float>(), sw.p32.as<float>(), vl, vl, st,
                          nr, s));
-  WF_TRY(operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr, nullptr,
-                                 sw.spec64.as<double2>(),
-                                 ZOUT_RES, sw.r64.as<double>(), sw.x64.as<double>(),
-                                 sw.b64.as<double>(), st, parts, nr, SKIP_UNLESS_UPDATE, s));
-  WF_HIP(launch_rel_reset(sw.r32.as<float>(), sw.r64.as<double>(), g.m, g.m, parts, st, nr, s));
+  if (sw.split) {
+    WF_TRY(split_passes<double>(od, SM_FWD_RES, sw.x64.as<double>(), sw.spec64.as<double2>(),
+                                sw.u64.as<double>(), sw.r64.as<double>(), sw.bh64.as<double>(), st,
+                                parts, nr, SKIP_UNLESS_UPDATE, s));
+  } else {
+    WF_TRY(operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr, nullptr,
+                                   sw.spec64.as<double2>(), ZOUT_RES, sw.r64.as<double>(),
+                                   sw.x64.as<double>(), sw.b64.as<double>(), st, parts, nr,
+                                   SKIP_UNLESS_UPDATE, s));
+  }
+  WF_HIP(launch_rel_reset(sw.r32.as<float>(), sw.r64.as<double>(), vl, vl, parts, st, nr, s));
   return {};
 }
 
-Status solve_true_residual(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s) {
-  return true_residual(od, sw, sw.q64.as<double>(), nr, s);
+Status solve_finish(const OperatorData& od, SolveWork& sw, int nr, bool mixed, hipStream_t s) {
+  if (!sw.split) {
+    if (!mixed) WF_TRY(true_residual(od, sw, sw.q64.as<double>(), nr, s));
+    return {};
+  }
+  const int64_t vl = sw.vlen;
+  CgState* st = sw.state.as<CgState>();
+  if (!mixed)
+    WF_HIP(launch_cg_flush<double>(sw.x64.as<double>(), sw.p64.as<double>(), vl, vl, st, nr, s));
+  // s = C y into x64 (stride n^3), then ||b - A s||^2 into outer_rr
+  WF_TRY(split_solution(od, sw.x64.as<double>(), sw.spec64.as<double2>(), sw.x64.as<double>(), nr,
+                        s));
+  return operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr, nullptr,
+                                 sw.spec64.as<double2>(), ZOUT_RES, sw.u64.as<double>(),
+                                 sw.x64.as<double>(), sw.b64.as<double>(), st,
+                                 sw.partials.as<double>(), nr, SKIP_NONE, s);
 }
 
-void solve_infos(const CgState* st, int nr, bool mixed, const Grid& g, double ms,
+void solve_infos(const CgState* st, int nr, bool mixed, bool split, const Grid& g, double ms,
                  wf_solve_info* infos) {
   const double M = (double)g.m;
   for (int i = 0; i < nr; ++i) {
@@ -206,12 +272,17 @@ void solve_infos(const CgState* st, int nr, bool mixed, const Grid& g, double ms
     in.iters_total = c.iter;
     in.outer_steps = mixed ? c.updates : 0;
     in.rel_res_recursive = c.bnorm > 0 ? c.rel : 0.0;
-    in.rel_res_true = c.bnorm > 0 ? std::sqrt(c.outer_rr) / c.bnorm : 0.0;
+    const double bn = split ? c.onorm : c.bnorm;
+    in.rel_res_true = bn > 0 ? std::sqrt(c.outer_rr) / bn : 0.0;
     in.time_ms = ms;
     // mixed: FP32 iterations; per update: fold (x64 rw, x32 rw), FP64 residual, reset
-    in.model_bytes = mixed ? (c.iter * model_bytes_iteration(false) +
-                              c.updates * (model_bytes_residual() + 24.0 + 12.0) + 40.0) * M
-                           : (c.iter * model_bytes_iteration(true) + model_bytes_residual()) * M;
+    const double it = model_bytes_iteration(false, split), it64 = model_bytes_iteration(true, split);
+    const double res = model_bytes_residual(split);
+    double mb = mixed ? c.iter * it + c.updates * (res + 24.0 + 12.0) + 40.0
+                      : c.iter * it64 + (split ? 0.0 : model_bytes_residual(false));
+    // split: C b and ||b|| at the start; C y and ||b - A s|| at the end
+    if (split) mb += 3 * 16.0 + 8.0 + 3 * 16.0 + model_bytes_residual(false);
+    in.model_bytes = mb * M;
     in.nbar = c.nbar;
     in.status = map_cg_status(c.status);
   }
@@ -225,8 +296,9 @@ Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
   const hipStream_t s = rq.stream;
   const wf_solve_opts& o = rq.opts;
   const bool mixed = o.precision == WF_MIXED;
+  const bool split = o.precond == WF_PRECOND_PRIOR;
   const int check = o.check_every > 0 ? o.check_every : 16;
-  WF_TRY(sw.ensure(*rq.al, g, nr, !mixed, mixed));
+  WF_TRY(sw.ensure(*rq.al, g, nr, !mixed, mixed, split));
   std::vector<CgState> st(nr);
   for (int i = 0; i < nr; ++i) {
     st[i] = CgState{};
@@ -240,15 +312,12 @@ Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
   Timer tm;
   tm.start(s);
   WF_TRY(solve_start(od, sw, nr, mixed, s));
-  if (mixed) {
-    WF_TRY(iterate_reliable(od, sw, nr, check, s));
-  } else {
-    WF_TRY(iterate_until_done<double>(od, sw, v64(sw), nr, check, s));
-    WF_TRY(solve_true_residual(od, sw, nr, s));
-  }
+  if (mixed) WF_TRY(iterate_reliable(od, sw, nr, check, s));
+  else WF_TRY(iterate_until_done<double>(od, sw, v64(sw), nr, check, s));
+  WF_TRY(solve_finish(od, sw, nr, mixed, s));
   const double ms = tm.stop(s);
   WF_TRY(sw.pull_state(s));
-  solve_infos(sw.st_host, nr, mixed, g, ms, infos);
+  solve_infos(sw.st_host, nr, mixed, split, g, ms, infos);
   Status worst{};
   for (int i = 0; i < nr; ++i) {
     const wf_status stt = (wf_status)infos[i].status;
@@ -356,7 +425,8 @@ Status run_batch(const OperatorData& od, const Allocator& al, DepositWork& dw,
   const Grid& g = od.g;
   const int nr = bi.nrhs;
   SolveWork sw;
-  WF_TRY(sw.ensure(al, g, nr, o.precision == WF_FP64, o.precision == WF_MIXED));
+  WF_TRY(sw.ensure(al, g, nr, o.precision == WF_FP64, o.precision == WF_MIXED,
+                   o.precond == WF_PRECOND_PRIOR));
   DevBuf xyz, nobs, scal, flag;
   WF_TRY(nobs.ensure(al, (size_t)g.m * 8));
   WF_TRY(scal.ensure(al, (size_t)(2 + nr) * 8));
@@ -403,14 +473,17 @@ Status run_batch(const OperatorData& od, const Allocator& al, DepositWork& dw,
   return r;
 }
 
-size_t footprint_bytes(int n, int ss, wf_precision prec, int nrhs) {
+size_t footprint_bytes(int n, int ss, wf_precision prec, int nrhs, bool split) {
   if (n <= 0 || nrhs <= 0 || (ss != 1 && ss != 2)) return 0;
   Grid g;
   g.set(n, 1.0);
   const double M = (double)g.m, ST = (double)g.spec_total;
+  const double V = split ? 2.0 * ST : M;  // elements of one CG vector
   double op = 12.0 * M + 8.0 * g.lamlen + 12.0 * g.xlamlen + 24.0 * n;
-  double per = 24.0 * M + 16.0 * ST;                      // b, x, r, spec64
-  per += prec == WF_FP64 ? 16.0 * M : 16.0 * M + 8.0 * ST;  // p, q | 4 FP32 vectors, spec32
+  if (split) op += 12.0 * (double)split_fac_elems(n);
+  double per = 8.0 * M + 16.0 * V + 16.0 * ST;              // b, x, r, spec64
+  per += prec == WF_FP64 ? 16.0 * V : 16.0 * V + 8.0 * ST;  // p, q | 4 FP32 vectors, spec32
+  if (split) per += 8.0 * V + 8.0 * M + (prec == WF_MIXED ? 4.0 * M : 0.0);  // C b, scratch
   const int nf = ss * n;
   double dep = 8.0 * (double)nf * nf * nf + 8.0 * M;  // integer grid, n_obs
   if (ss == 2)

@@ -119,3 +119,20 @@ def test_deposit_order_independent(ctx):
     g2, _, _ = ctx.get_deposit(True, False, 2)
     assert np.array_equal(g1, g2)
     assert int(g1.sum()) == len(xyz) << 39
+
+
+def test_supersample_after_a_larger_grid(ctx):
+    """One context reused from a larger to smaller grids: the fine-grid FFT
+    tables follow the grid (a 48^3 fine grid after a 64^3 one once kept the
+    64-point twiddles)."""
+    box = 150.0
+    for n in (32, 24, 16):
+        xyz = synth.uniform_catalogue(4000, box, seed=100 + n)
+        w = synth.cap_mask(n, box, 70.0, 120.0)
+        ctx.set_grid(n, box)
+        ctx.set_mask(w)
+        ctx.set_galaxies(xyz)
+        ctx.deposit("cic", 2)
+        _, nobs, _ = ctx.get_deposit(False, True, 2)
+        ref_nobs, _ = oss.observed_counts(xyz, n, box, "cic", 2)
+        assert rel_max(nobs, ref_nobs) < 1e-13

@@ -1,0 +1,193 @@
+"""GPU parity of the prior-split CG, (C A C) y = C b with s = C y (C the square
+root of the prior covariance, Sec. 3.3.1), against the oracle's split_cg,
+through the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import wiener as ow
+
+from gpu_util import context, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+WF_OK, WF_EINVAL, WF_ENOTCONV = 0, 1, 5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = context()
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def bbks48():
+    """48^3 / 500 Mpc, BBKS prior, cap mask, lognormal-Poisson catalogue,
+    2x supersampled CIC (the plain solver's fixed-k parity workload)."""
+    wl = synth.Workload("bbks48", 48, 500.0, "cic", 2, 60000, 211, "bbks")
+    ptab = wl.ptab()
+    w = wl.mask()
+    cat = wl.catalogue(ptab, w)
+    res = ow.reconstruct(cat.xyz, wl.n, wl.box, w, ptab, "cic", 2, 1e-10, 5000)
+    ref = ow.reference_solution(res["system"], res["b"], tol=1e-13)
+    return dict(wl=wl, ptab=ptab, w=w, xyz=cat.xyz, res=res, x_ref=ref["x"])
+
+
+def _load(ctx, d):
+    wl = d["wl"]
+    ctx.set_grid(wl.n, wl.box)
+    ctx.set_mask(d["w"])
+    ctx.set_power(d["ptab"])
+    ctx.set_galaxies(d["xyz"])
+    ctx.deposit("cic", 2)
+
+
+@pytest.mark.parametrize("k,tol", [(1, 1e-13), (20, 1e-8), (80, 1e-7), (200, 1e-12)])
+def test_fixed_iteration_parity_split_fp64(ctx, bbks48, k, tol):
+    """Both sides run exactly k iterations of CG on C A C from y = 0.  The
+    tolerance is ten times the oracle's own spread at that k: with 1e-16
+    relative noise added to each operator application its iterates move by
+    7.8e-10 at k = 20, 1.1e-8 at k = 80 (the phase where the large
+    eigenvalues are being resolved) and 2e-14 at k = 200."""
+    d = bbks48
+    _load(ctx, d)
+    x, info = ctx.solve(precision="fp64", precond="prior", tol=0.0, max_iter=k,
+                        allow=(WF_ENOTCONV,))
+    assert info.iters_total == k and info.status == WF_ENOTCONV
+    ref = ow.split_cg(d["res"]["system"], d["res"]["b"], 0.0, k)
+    err = rel_l2(x, ref["x"])
+    print(f"split fixed k={k}: rel_l2 {err:.3e} rec {info.rel_res_recursive:.6e} "
+          f"vs {ref['rel_res']:.6e}")
+    assert err < tol
+    # residuals relative to ||C b|| and ||b||: their spread follows the iterates'
+    assert abs(info.rel_res_recursive - ref["rel_res"]) < max(1e-12, tol)
+    assert abs(info.rel_res_true - ref["rel_res_true"]) < max(1e-12, tol)
+
+
+def test_split_converged_fp64(ctx, bbks48):
+    d = bbks48
+    _load(ctx, d)
+    x, info = ctx.solve(precision="fp64", precond="prior", tol=1e-12, max_iter=5000)
+    assert info.status == WF_OK
+    assert info.rel_res_recursive <= 1e-12
+    assert rel_l2(x, d["x_ref"]) < 1e-10
+    assert info.rel_res_true < 1e-9
+
+
+def test_split_needs_fewer_iterations(ctx, bbks48):
+    d = bbks48
+    _load(ctx, d)
+    _, plain = ctx.solve(precision="fp64", tol=1e-8, max_iter=20000)
+    x, split = ctx.solve(precision="fp64", precond="prior", tol=1e-8, max_iter=20000)
+    print(f"iterations to 1e-8: plain {plain.iters_total} split {split.iters_total}")
+    assert split.iters_total < plain.iters_total
+    assert rel_l2(x, d["x_ref"]) < 1e-6
+
+
+@pytest.mark.parametrize("tol", [1e-7, 1e-10])
+def test_split_mixed(ctx, bbks48, tol):
+    """FP32 operator and vectors with FP64 reliable updates on the split
+    system; convergence is decided on the FP64 split residual."""
+    d = bbks48
+    _load(ctx, d)
+    x, info = ctx.solve(precision="mixed", precond="prior", tol=tol, max_iter=20000)
+    assert info.status == WF_OK
+    assert info.outer_steps >= 1
+    err = rel_l2(x, d["x_ref"])
+    # the oracle recomputes the split residual ||C (b - A s)|| / ||C b|| of the
+    # returned solution: the device stopped on the same quantity in FP64
+    sysm = d["res"]["system"]
+    b = d["res"]["b"]
+    sp = ow.SplitSystem(sysm)
+    r = sp.split(b - sysm.apply(x))
+    rel = float(np.linalg.norm(r) / np.linalg.norm(sp.split(b)))
+    print(f"split mixed tol={tol:g}: iters {info.iters_total} updates {info.outer_steps} "
+          f"split res {rel:.3e} err {err:.3e} true res {info.rel_res_true:.3e}")
+    assert rel <= 1.01 * tol
+    # error per unit of split residual on this workload: ~2 early, ~120 once the
+    # small-scale modes dominate what is left (FP64 reaches 1e-12 -> err < 1e-10)
+    assert err < 300 * tol
+    # the same solve twice gives the same bits
+    y, _ = ctx.solve(precision="mixed", precond="prior", tol=tol, max_iter=20000)
+    assert np.array_equal(x, y)
+
+
+def test_split_zero_rhs(ctx, bbks48):
+    d = bbks48
+    wl = d["wl"]
+    ctx.set_grid(wl.n, wl.box)
+    ctx.set_mask(d["w"])
+    ctx.set_power(d["ptab"])
+    ctx.set_rhs(np.zeros((wl.n,) * 3), 1.0)
+    for prec in ("fp64", "mixed"):
+        x, info = ctx.solve(precision=prec, precond="prior", tol=1e-10, max_iter=100)
+        assert info.status == WF_OK and info.iters_total == 0
+        assert not x.any()
+
+
+def test_split_batch_equals_single():
+    wl = synth.Workload("b32", 32, 300.0, "cic", 2, 30000, 401, "bbks")
+    ptab = wl.ptab()
+    w = wl.mask()
+    cats = []
+    for j in range(3):
+        wl.seed = 401 + 3 * j
+        cats.append(wl.catalogue(ptab, w).xyz)
+    ctx = context()
+    ctx.set_grid(wl.n, wl.box)
+    ctx.set_mask(w)
+    ctx.set_power(ptab)
+    for prec in ("mixed", "fp64"):
+        outs, infos = ctx.solve_batch(cats, "cic", 2, precision=prec, precond="prior", tol=1e-9,
+                                      max_iter=20000)
+        for xyz, x, info in zip(cats, outs, infos):
+            assert info.status == WF_OK
+            ctx.set_galaxies(xyz)
+            ctx.deposit("cic", 2)
+            y, inf1 = ctx.solve(precision=prec, precond="prior", tol=1e-9, max_iter=20000)
+            assert np.array_equal(x, y)
+            assert info.iters_total == inf1.iters_total
+    res = ow.reconstruct(cats[1], wl.n, wl.box, w, ptab, "cic", 2, 1e-12, 20000)
+    assert rel_l2(outs[1], res["x"]) < 1e-6
+    ctx.close()
+
+
+def test_split_server_equals_context():
+    import paper_0906_3978_amd as wf
+    reqs = []
+    for i, n in enumerate([16, 32, 24]):
+        wl = synth.serving_request(i, base_seed=950, box=300.0, grids=(n,))
+        wl.n_target = min(wl.n_target, 30000)
+        ptab = wl.ptab()
+        w = wl.mask()
+        reqs.append((wl, ptab, w, wl.catalogue(ptab, w).xyz))
+    kw = dict(precision="mixed", precond="prior", tol=1e-9, max_iter=20000)
+    with wf.Server(0, hbm_budget=1 << 30, max_active=4) as srv:
+        tickets = [srv.submit(wl.n, wl.box, w, p, xyz, "cic", 2, **kw) for wl, p, w, xyz in reqs]
+        got = [srv.wait(t, wl.n) for t, (wl, _, _, _) in zip(tickets, reqs)]
+    ctx = context()
+    for (wl, p, w, xyz), (x, info) in zip(reqs, got):
+        assert info.status == WF_OK
+        ctx.set_grid(wl.n, wl.box)
+        ctx.set_mask(w)
+        ctx.set_power(p)
+        ctx.set_galaxies(xyz)
+        ctx.deposit("cic", 2)
+        y, inf1 = ctx.solve(**kw)
+        assert np.array_equal(x, y)
+        assert info.iters_total == inf1.iters_total
+    ctx.close()
+
+
+def test_split_option_checks(ctx, bbks48):
+    import ctypes
+    import paper_0906_3978_amd as wf
+    _load(ctx, bbks48)
+    o = wf.opts(precision="fp64", tol=1e-8)
+    o.precond = 7
+    L = wf.lib()
+    out = np.empty((48,) * 3)
+    assert L.wf_solve(ctx._h, ctypes.byref(o), out.ctypes.data, 0, None) == WF_EINVAL
+    with pytest.raises(wf.WienerError):
+        ctx.solve_begin(precision="fp64", precond="prior", tol=1e-8)
