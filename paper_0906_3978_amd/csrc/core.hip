@@ -164,7 +164,6 @@ Status SolveWork::ensure(const Allocator& al, const Grid& g, int nr, bool fp64_c
   if (split) {
     WF_TRY(bh64.ensure(al, v * 8));
     WF_TRY(u64.ensure(al, m * 8));
-    if (mixed) WF_TRY(u32.ensure(al, m * 4));
   }
   // partials: enough for the largest grid of any reduction kernel per RHS
   const int64_t zblocks = g.nrows / 2;  // upper bound of z-pass blocks (NB >= 1)
@@ -456,15 +455,25 @@ static StrArgs<T> split_x_args(const OperatorData& od, const cplx<T>* in, cplx<T
 }
 
 template <typename T>
-Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* work, T* u, T* out,
+Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* work, T* out,
                     const double* bh, CgState* st, double* partials, int nrhs, int skip,
-                    hipStream_t s) {
+                    hipStream_t s, const T* rdir, T* xdir) {
   const Grid& g = od.g;
   const bool f64 = sizeof(T) == 8;
   const double vb = (double)sizeof(T) * g.m * nrhs;
   const double sb = 2.0 * sizeof(T) * g.spec_total * nrhs;
   const cplx<T>* pc = reinterpret_cast<const cplx<T>*>(pin);
-  {
+  if (rdir) {
+    // CG: r, p, x in; p, x and the x-transformed work spectrum out
+    ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 6 * sb, s);
+    StrArgs<T> xa = split_x_args<T>(od, reinterpret_cast<const cplx<T>*>(rdir), work, nullptr,
+                                    nullptr, st, skip, nullptr);
+    xa.s0.p = const_cast<cplx<T>*>(pc);
+    xa.s1.p = xa.s0.p + g.spec_main;
+    xa.s0.x = reinterpret_cast<cplx<T>*>(xdir);
+    xa.s1.x = xa.s0.x + g.spec_main;
+    WF_HIP(launch_strided<T>(g.n, SM_INV_DIR, xa, nrhs, s));
+  } else {
     // p in, scaled and transformed along x into the work spectrum
     ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 2 * sb, s);
     WF_HIP(launch_strided<T>(g.n, SM_INV_SCALE,
@@ -476,37 +485,19 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
     WF_HIP(launch_strided<T>(g.n, SM_INV, str_args<T>(od, work, false, st, skip), nrhs, s));
   }
   {
-    ZinvArgs<T> zi{};
-    zi.in_main = work;
-    zi.in_nyq = work + g.spec_main;
-    zi.rhs_main = g.spec_total;
-    zi.rhs_nyq = g.spec_total;
-    zi.out = u;
-    zi.rhs_out = g.m;
-    zi.w = w_of<T>(od);
-    zi.scale = 1.0;
-    zi.tw = tw_of<T>(od);
-    zi.st = st;
-    zi.skip = skip;
-    // spectrum in, w in (once), real field out
+    ZmidArgs<T> zm{};
+    zm.spec_main = work;
+    zm.spec_nyq = work + g.spec_main;
+    zm.rhs_main = g.spec_total;
+    zm.rhs_nyq = g.spec_total;
+    zm.w = w_of<T>(od);
+    zm.tw = tw_of<T>(od);
+    zm.st = st;
+    zm.skip = skip;
+    // spectrum in and out, w in (once for all RHS)
     ProfScope ps(od.prof, f64 ? WF_PROF_SZW_F64 : WF_PROF_SZW_F32,
-                 sb / 2 + vb + (double)sizeof(T) * g.m, s);
-    WF_HIP(launch_zinv<T>(g.n, ZOUT_W, zi, g.nrows, nrhs, s));
-  }
-  {
-    ZfwdArgs<T> zf{};
-    zf.in = u;
-    zf.out_main = work;
-    zf.out_nyq = work + g.spec_main;
-    zf.nkz_out = g.n / 2;
-    zf.rhs_in = g.m;
-    zf.rhs_main = g.spec_total;
-    zf.rhs_nyq = g.spec_total;
-    zf.tw = tw_of<T>(od);
-    zf.st = skip != SKIP_NONE ? st : nullptr;
-    zf.skip = skip;
-    ProfScope ps(od.prof, f64 ? WF_PROF_ZFWD_F64 : WF_PROF_ZFWD_F32, vb + sb / 2, s);
-    WF_HIP(launch_zfwd<T>(g.n, ZIN_REAL, zf, g.nrows, nrhs, s));
+                 sb + (double)sizeof(T) * g.m, s);
+    WF_HIP(launch_zmid<T>(g.n, zm, g.nrows, nrhs, s));
   }
   {
     ProfScope ps(od.prof, f64 ? WF_PROF_YFWD_F64 : WF_PROF_YFWD_F32, 2 * sb, s);
@@ -517,7 +508,7 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
                                         partials);
   {
     // work spectrum in, result out; CGQ also reads p, RES y and b (FP64)
-    double xb = sb;
+    double xb = 2 * sb;
     if (mode == SM_FWD_CGQ) xb += sb;
     if (mode == SM_FWD_RES) xb += 2 * sb;
     ProfScope ps(od.prof, f64 ? WF_PROF_SXFWD_F64 : WF_PROF_SXFWD_F32, xb, s);
@@ -529,11 +520,11 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
   return {};
 }
 template Status split_passes<float>(const OperatorData&, int, const float*, cplx<float>*, float*,
-                                    float*, const double*, CgState*, double*, int, int,
-                                    hipStream_t);
+                                    const double*, CgState*, double*, int, int, hipStream_t,
+                                    const float*, float*);
 template Status split_passes<double>(const OperatorData&, int, const double*, cplx<double>*,
-                                     double*, double*, const double*, CgState*, double*, int, int,
-                                     hipStream_t);
+                                     double*, const double*, CgState*, double*, int, int,
+                                     hipStream_t, const double*, double*);
 
 // b_hat = c sqrt(D) F b (FP64, one RHS after another share the launches)
 Status split_rhs(const OperatorData& od, const double* b, cplx<double>* work, double* bh,

@@ -271,10 +271,6 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
       const T sc = (T)a.scale;
       st16(out + i0, re * sc);
       st16(out + i1, imv * sc);
-    } else if constexpr (MODE == ZOUT_W) {
-      const R w0 = ld16(a.w + i0), w1 = ld16(a.w + i1);
-      st16(out + i0, (nbar * w0) * re);
-      st16(out + i1, (nbar * w1) * imv);
     } else if constexpr (MODE == ZOUT_CGQ || MODE == ZOUT_APPLY) {
       const T* p = a.aux + rhs * a.rhs_aux;
       const R p0 = ld16(p + i0), p1 = ld16(p + i1);
@@ -308,44 +304,178 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// z middle pass of the prior-split operator: half spectrum -> real rows ->
+// times nbar w -> half spectrum, in place (the rows of a block are its own)
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_zmid(ZmidArgs<T> a) {
+  using V = cplx<T>;
+  using R = vec16<T>;
+  constexpr int RW = 16 / sizeof(T);
+  constexpr int CW = 16 / sizeof(V);
+  constexpr int NB = z_nb<T, N>();
+  constexpr int H = N / 2;
+  __shared__ __align__(16) V lds[NB * N];
+  __shared__ V twl[N];
+  const int rhs = blockIdx.y;
+  const CgState* st = a.st + rhs;
+  if (skip_rhs(st, a.skip)) return;
+  const int64_t row0 = (int64_t)blockIdx.x * NB * 2;
+  load_twiddles<T, N, NT>(twl, a.tw);
+  V* sm = a.spec_main + rhs * a.rhs_main;
+  V* sq = a.spec_nyq + rhs * a.rhs_nyq;
+
+  // rows r0, r0 + 1 as Z = A + i B (only the real parts of k = 0 and N/2 enter)
+  constexpr int ITEMS = NB * H / CW;
+  constexpr int PER = (ITEMS + NT - 1) / NT;
+  R va[PER], vb[PER];
+#pragma unroll
+  for (int c = 0; c < PER; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (ITEMS % NT == 0 || q < ITEMS) {
+      const int b = q / (H / CW), k0 = (q - b * (H / CW)) * CW;
+      const int64_t r0 = row0 + 2 * b;
+      va[c] = ld16(reinterpret_cast<const T*>(sm + r0 * H + k0));
+      vb[c] = ld16(reinterpret_cast<const T*>(sm + (r0 + 1) * H + k0));
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < PER; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (ITEMS % NT == 0 || q < ITEMS) {
+      const int b = q / (H / CW), k0 = (q - b * (H / CW)) * CW;
+#pragma unroll
+      for (int j = 0; j < CW; ++j) {
+        const int k = k0 + j;
+        const T ax = va[c][2 * j], ay = va[c][2 * j + 1];
+        const T bx = vb[c][2 * j], by = vb[c][2 * j + 1];
+        if (k == 0) {
+          lds[b * N] = V{ax, bx};
+        } else {
+          lds[b * N + k] = V{ax - by, ay + bx};
+          lds[b * N + N - k] = V{ax + by, bx - ay};
+        }
+      }
+    }
+  }
+  for (int b = threadIdx.x; b < NB; b += NT) {
+    const int64_t r0 = row0 + 2 * b;
+    lds[b * N + H] = V{sq[r0].x, sq[r0 + 1].x};
+  }
+  __syncthreads();
+  fft_tile<T, N, NB, NT, false, +1>(lds, twl);
+
+  // real rows (re: r0, im: r0 + 1) times nbar w
+  const T nbar = (T)st->nbar;
+  constexpr int ITEMS3 = NB * N / RW;
+  constexpr int PER3 = (ITEMS3 + NT - 1) / NT;
+#pragma unroll
+  for (int c = 0; c < PER3; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (ITEMS3 % NT == 0 || q < ITEMS3) {
+      const int b = q / (N / RW), z = (q - b * (N / RW)) * RW;
+      const int64_t i0 = (row0 + 2 * b) * N + z;
+      const R w0 = nbar * ld16(a.w + i0), w1 = nbar * ld16(a.w + i0 + N);
+#pragma unroll
+      for (int j = 0; j < RW; ++j) {
+        const V v = lds[b * N + z + j];
+        lds[b * N + z + j] = V{v.x * w0[j], v.y * w1[j]};
+      }
+    }
+  }
+  __syncthreads();
+  fft_tile<T, N, NB, NT, false, -1>(lds, twl);
+
+  // split the two real rows: A_k = (Z_k + conj Z_-k)/2, B_k = (Z_k - conj Z_-k)/(2i)
+#pragma unroll
+  for (int c = 0; c < PER; ++c) {
+    const int q = threadIdx.x + c * NT;
+    if (!(ITEMS % NT == 0 || q < ITEMS)) continue;
+    const int b = q / (H / CW), k0 = (q - b * (H / CW)) * CW;
+    R oa, ob;
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      const int k = k0 + j;
+      const V zk = lds[b * N + k];
+      const V zn = lds[b * N + ((N - k) % N)];
+      oa[2 * j] = T(0.5) * (zk.x + zn.x);
+      oa[2 * j + 1] = T(0.5) * (zk.y - zn.y);
+      ob[2 * j] = T(0.5) * (zk.y + zn.y);
+      ob[2 * j + 1] = T(-0.5) * (zk.x - zn.x);
+    }
+    const int64_t r0 = row0 + 2 * b;
+    st16(reinterpret_cast<T*>(sm + r0 * H + k0), oa);
+    st16(reinterpret_cast<T*>(sm + (r0 + 1) * H + k0), ob);
+  }
+  for (int b = threadIdx.x; b < NB; b += NT) {
+    const V zh = lds[b * N + H];
+    const int64_t r0 = row0 + 2 * b;
+    sq[r0] = V{zh.x, T(0)};
+    sq[r0 + 1] = V{zh.y, T(0)};
+  }
+}
+
+// ---------------------------------------------------------------------------
 // strided passes (y or x axis)
 // ---------------------------------------------------------------------------
-// Prior-split factor c of the x-pass element at x index i of column cb
-// (Seg fields give the column's |my| and kz); flags the monopole.
-template <typename T, int N>
-__device__ __forceinline__ T split_c(const T* __restrict__ fac, const Seg<T>& s, int outer, int cb,
-                                     int i, int& kz, bool& dc) {
-  constexpr int H = N / 2 + 1;
-  int my = s.lam_y_outer ? signed_m(outer, N) : signed_m(cb, N);
-  my = my < 0 ? -my : my;
-  kz = s.lam_kz < 0 ? cb : s.lam_kz;
+// Row stride of the prior-split factor table [|my|][|mx|][kz] (kz < N/2 + 1,
+// padded to an even count so that kz pairs load as one aligned vector).
+template <int N> constexpr int split_row() { return (N / 2 + 2) & ~1; }
+
+// Prior-split factors c of the CW elements at x index i, columns cb..cb+CW-1
+// of an x-pass segment (its fields give each column's |my| and kz), with the
+// kz plane of each and whether it is the monopole.
+template <typename T, int N, int CW>
+__device__ __forceinline__ void split_facs(const T* __restrict__ fac, const Seg<T>& s, int outer,
+                                           int cb, int i, T* f, int* kz, bool* dc) {
+  constexpr int H = N / 2 + 1, HP = split_row<N>();
   int mx = signed_m(i, N);
   mx = mx < 0 ? -mx : mx;
-  dc = (my | mx | kz) == 0;
-  return fac[((int64_t)my * H + mx) * H + kz];
+  if (s.lam_kz < 0) {  // columns are kz = cb + j of the row my = outer
+    int my = signed_m(outer, N);
+    my = my < 0 ? -my : my;
+    const T* row = fac + ((int64_t)my * H + mx) * HP + cb;
+    if constexpr (CW == 2 && sizeof(T) == 4) {
+      const float2 v = *reinterpret_cast<const float2*>(row);
+      f[0] = v.x;
+      f[1] = v.y;
+    } else {
+#pragma unroll
+      for (int j = 0; j < CW; ++j) f[j] = row[j];
+    }
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      kz[j] = cb + j;
+      dc[j] = (my | mx | kz[j]) == 0;
+    }
+  } else {  // columns are my = cb + j of the plane kz = lam_kz
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      int my = signed_m(cb + j, N);
+      my = my < 0 ? -my : my;
+      kz[j] = s.lam_kz;
+      f[j] = fac[((int64_t)my * H + mx) * HP + s.lam_kz];
+      dc[j] = false;
+    }
+  }
 }
 // sqrt(D) of a kz plane (D = 1 on kz = 0 and kz = N/2, else 2)
 template <typename T, int N> __device__ __forceinline__ T sqrt_d(int kz) {
   return (kz == 0 || kz == N / 2) ? T(1) : T(1.41421356237309504880168872420969808);
 }
 
-// Output value of the split modes from the forward-transformed element v.
+// Output value of the split modes from the forward-transformed element v
+// (f: factor, pv: aux value, bv: b value).
 template <typename T, int N, int MODE>
-__device__ __forceinline__ cplx<T> split_out(const StrArgs<T>& a, const Seg<T>& s, int outer, int cb,
-                                            int i, cplx<T> v, const cplx<T>* auxp,
-                                            const cplx<double>* bp, double& acc) {
-  int kz;
-  bool dc;
-  const T f = split_c<T, N>(a.fac, s, outer, cb, i, kz, dc) * sqrt_d<T, N>(kz);
+__device__ __forceinline__ cplx<T> split_out(T f, int kz, bool dc, cplx<T> v, cplx<T> pv,
+                                            cplx<double> bv, double& acc) {
+  f *= sqrt_d<T, N>(kz);
   cplx<T> o = {f * v.x, f * v.y};
   if constexpr (MODE == SM_FWD_CGQ) {
-    const cplx<T> pv = *auxp;
     if (!dc) o = cadd(o, pv);
     acc += (double)pv.x * (double)o.x + (double)pv.y * (double)o.y;
   } else if constexpr (MODE == SM_FWD_RES) {
-    const cplx<T> yv = *auxp;
-    if (!dc) o = cadd(o, yv);
-    const cplx<double> bv = *bp;
+    if (!dc) o = cadd(o, pv);
     o = {(T)(bv.x - (double)o.x), (T)(bv.y - (double)o.y)};
     acc += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
   }
@@ -355,7 +485,10 @@ __device__ __forceinline__ cplx<T> split_out(const StrArgs<T>& a, const Seg<T>& 
 template <typename T, int N, int MODE, int TB, int NTS>
 __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   constexpr int NT = NTS;
-  constexpr bool NTA = (MODE == SM_FWD_LAM_INV);  // nontemporal in the x pass only
+  // nontemporal in the x pass only
+  constexpr bool NTA = MODE == SM_FWD_LAM_INV || MODE == SM_INV_SCALE || MODE == SM_INV_DIR ||
+                       MODE == SM_FWD_SCALE || MODE == SM_FWD_CGQ || MODE == SM_FWD_RES;
+  constexpr bool SCALE_IN = MODE == SM_INV_SCALE || MODE == SM_INV_DIR;
   using V = cplx<T>;
   using R = vec16<T>;
   constexpr int CW = 16 / sizeof(V);
@@ -390,20 +523,45 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           buf[c] = ld16x<NTA>(reinterpret_cast<const T*>(in + i * s.in_axis + b));
         }
       }
+      if constexpr (MODE == SM_INV_DIR) {
+        // CG direction: `in` is r; the pending x += alpha p, then p = r + beta p
+        const CgState* cs = a.st + rhs;
+        const bool first = cs->first != 0, pending = cs->pending != 0;
+        const T alpha = (T)cs->alpha, beta = (T)cs->beta;
+        const int64_t vo = rhs * s.in_rhs + outer * s.in_outer + b0 * s.in_batch;
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+          const int q = threadIdx.x + c * NT;
+          if (ITEMS % NT == 0 || q < ITEMS) {
+            const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+            T* pp = reinterpret_cast<T*>(s.p + vo + i * s.in_axis + b);
+            if (!first) {
+              const R pv = ld16x<NTA>(pp);
+              if (pending) {
+                T* xp = reinterpret_cast<T*>(s.x + vo + i * s.in_axis + b);
+                st16x<NTA>(xp, ld16x<NTA>(xp) + alpha * pv);
+              }
+              buf[c] += beta * pv;
+            }
+            st16x<NTA>(pp, buf[c]);
+          }
+        }
+      }
 #pragma unroll
       for (int c = 0; c < PER; ++c) {
         const int q = threadIdx.x + c * NT;
         if (ITEMS % NT == 0 || q < ITEMS) {
-          if constexpr (MODE == SM_INV_SCALE) {
+          if constexpr (SCALE_IN) {
             const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+            T f[CW];
+            int kz[CW];
+            bool dc[CW];
+            split_facs<T, N, CW>(a.fac, s, outer, b0 + b, i, f, kz, dc);
 #pragma unroll
             for (int j = 0; j < CW; ++j) {
-              int kz;
-              bool dc;
-              const T f = split_c<T, N>(a.fac, s, outer, b0 + b + j, i, kz, dc) *
-                          ((T)a.in_scale / sqrt_d<T, N>(kz));
-              buf[c][2 * j] *= f;
-              buf[c][2 * j + 1] *= f;
+              const T g = f[j] * ((T)a.in_scale / sqrt_d<T, N>(kz[j]));
+              buf[c][2 * j] *= g;
+              buf[c][2 * j + 1] *= g;
             }
           }
           *reinterpret_cast<R*>(lds + q * CW) = buf[c];
@@ -413,11 +571,26 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
       for (int e = threadIdx.x; e < TB * N; e += NT) {
         const int b = e % TB, i = e / TB;
         V v = in[i * s.in_axis + b];
-        if constexpr (MODE == SM_INV_SCALE) {
+        if constexpr (MODE == SM_INV_DIR) {
+          const CgState* cs = a.st + rhs;
+          const int64_t o = rhs * s.in_rhs + outer * s.in_outer + b0 * s.in_batch + i * s.in_axis + b;
+          if (!cs->first) {
+            const V pv = s.p[o];
+            if (cs->pending) {
+              const T al = (T)cs->alpha;
+              s.x[o] = V{s.x[o].x + al * pv.x, s.x[o].y + al * pv.y};
+            }
+            const T be = (T)cs->beta;
+            v = V{v.x + be * pv.x, v.y + be * pv.y};
+          }
+          s.p[o] = v;
+        }
+        if constexpr (SCALE_IN) {
+          T f;
           int kz;
           bool dc;
-          const T f = split_c<T, N>(a.fac, s, outer, b0 + b, i, kz, dc) *
-                      ((T)a.in_scale / sqrt_d<T, N>(kz));
+          split_facs<T, N, 1>(a.fac, s, outer, b0 + b, i, &f, &kz, &dc);
+          f *= (T)a.in_scale / sqrt_d<T, N>(kz);
           v = {v.x * f, v.y * f};
         }
         lds[e] = v;
@@ -507,7 +680,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
     fft_tile_diag<T, N, TB, NT>(lds, twl, lamv);
   } else {
     __syncthreads();
-    if constexpr (MODE == SM_INV || MODE == SM_INV_SCALE) fft_tile<T, N, TB, NT, true, +1>(lds, twl);
+    if constexpr (MODE == SM_INV || SCALE_IN) fft_tile<T, N, TB, NT, true, +1>(lds, twl);
     else fft_tile<T, N, TB, NT, true, -1>(lds, twl);
   }
 
@@ -532,13 +705,19 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
           const int64_t off = ob + i * s.out_axis + b;
           const R v = *reinterpret_cast<const R*>(lds + q * CW);
+          R av{};
+          if constexpr (REDUCE) av = ld16x<NTA>(reinterpret_cast<const T*>(s.aux + off));
+          T f[CW];
+          int kz[CW];
+          bool dc[CW];
+          split_facs<T, N, CW>(a.fac, s, outer, b0 + b, i, f, kz, dc);
           R o;
 #pragma unroll
           for (int j = 0; j < CW; ++j) {
-            const cplx<T> r = split_out<T, N, MODE>(
-                a, s, outer, b0 + b + j, i, V{v[2 * j], v[2 * j + 1]},
-                REDUCE ? s.aux + off + j : nullptr,
-                MODE == SM_FWD_RES ? s.bvec + off + j : nullptr, acc);
+            cplx<double> bv{0.0, 0.0};
+            if constexpr (MODE == SM_FWD_RES) bv = s.bvec[off + j];
+            const cplx<T> r = split_out<T, N, MODE>(f[j], kz[j], dc[j], V{v[2 * j], v[2 * j + 1]},
+                                                    V{av[2 * j], av[2 * j + 1]}, bv, acc);
             o[2 * j] = r.x;
             o[2 * j + 1] = r.y;
           }
@@ -549,9 +728,14 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
       for (int e = threadIdx.x; e < TB * N; e += NT) {
         const int b = e % TB, i = e / TB;
         const int64_t off = ob + i * s.out_axis + b;
-        s.out[off] = split_out<T, N, MODE>(a, s, outer, b0 + b, i, lds[e],
-                                           REDUCE ? s.aux + off : nullptr,
-                                           MODE == SM_FWD_RES ? s.bvec + off : nullptr, acc);
+        T f;
+        int kz;
+        bool dc;
+        split_facs<T, N, 1>(a.fac, s, outer, b0 + b, i, &f, &kz, &dc);
+        const V pv = REDUCE ? s.aux[off] : V{T(0), T(0)};
+        cplx<double> bv{0.0, 0.0};
+        if constexpr (MODE == SM_FWD_RES) bv = s.bvec[off];
+        s.out[off] = split_out<T, N, MODE>(f, kz, dc, lds[e], pv, bv, acc);
       }
     }
     if constexpr (REDUCE) {
@@ -720,21 +904,24 @@ bool fft_length_supported(int n, bool fp64) {
 }
 
 int64_t split_fac_elems(int n) {
-  const int64_t h = n / 2 + 1;
-  return (n >= 8 && n % 2 == 0) ? h * h * h : 0;
+  const int64_t h = n / 2 + 1, hp = (n / 2 + 2) & ~1;
+  return (n >= 8 && n % 2 == 0) ? h * h * hp : 0;
 }
 
-__global__ void k_split_fac(const double* __restrict__ lam, int h, double m_cells, double* fac64,
-                            float* fac32) {
-  const int64_t total = (int64_t)h * h * h;
+__global__ void k_split_fac(const double* __restrict__ lam, int h, int hp, double m_cells,
+                            double* fac64, float* fac32) {
+  const int64_t total = (int64_t)h * h * hp;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const int my = (int)(i / ((int64_t)h * h));
-    const int mx = (int)((i / h) % h);
-    const int kz = (int)(i % h);
-    int64_t j = (int64_t)my * my + (int64_t)mx * mx + (int64_t)kz * kz;
-    if (j == 0) j = 1;  // the monopole takes the |m|^2 = 1 value
-    const double c = 1.0 / sqrt(lam[j] * m_cells);
+    const int kz = (int)(i % hp);
+    const int64_t row = i / hp;
+    const int my = (int)(row / h), mx = (int)(row % h);
+    double c = 0.0;  // padding
+    if (kz < h) {
+      int64_t j = (int64_t)my * my + (int64_t)mx * mx + (int64_t)kz * kz;
+      if (j == 0) j = 1;  // the monopole takes the |m|^2 = 1 value
+      c = 1.0 / sqrt(lam[j] * m_cells);
+    }
     fac64[i] = c;
     fac32[i] = (float)c;
   }
@@ -745,8 +932,8 @@ hipError_t launch_split_fac(int n, const double* lam, double m_cells, double* fa
   const int64_t total = split_fac_elems(n);
   if (total <= 0) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_split_fac, dim3(blocks), dim3(256), 0, s, lam, n / 2 + 1, m_cells, fac64,
-                     fac32);
+  hipLaunchKernelGGL(k_split_fac, dim3(blocks), dim3(256), 0, s, lam, n / 2 + 1, (n / 2 + 2) & ~1,
+                     m_cells, fac64, fac32);
   return hipGetLastError();
 }
 
@@ -832,9 +1019,16 @@ static hipError_t zinv_n(int mode, const ZinvArgs<T>& a, int64_t nrows, int nrhs
       }
       return hipErrorInvalidValue;
     case ZOUT_APPLY: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_APPLY>), grid, dim3(NT), 0, s, a); break;
-    case ZOUT_W: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_W>), grid, dim3(NT), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t zmid_n(const ZmidArgs<T>& a, int64_t nrows, int nrhs, hipStream_t s) {
+  constexpr int NB = z_nb<T, N>();
+  dim3 grid((unsigned)(nrows / (2 * NB)), (unsigned)nrhs);
+  hipLaunchKernelGGL((k_zmid<T, N>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -851,12 +1045,15 @@ static hipError_t strided_v(int mode, const StrArgs<T>& a, int nrhs, hipStream_t
       hipLaunchKernelGGL((k_strided<T, N, SM_FWD_CROP, TBV, NTV>), grid, dim3(NTV), 0, s, a);
       break;
     case SM_INV_SCALE:
+    case SM_INV_DIR:
     case SM_FWD_SCALE:
     case SM_FWD_CGQ:
     case SM_FWD_RES:
       if constexpr (N <= 512) {
         if (mode == SM_INV_SCALE)
           hipLaunchKernelGGL((k_strided<T, N, SM_INV_SCALE, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+        else if (mode == SM_INV_DIR)
+          hipLaunchKernelGGL((k_strided<T, N, SM_INV_DIR, TBV, NTV>), grid, dim3(NTV), 0, s, a);
         else if (mode == SM_FWD_SCALE)
           hipLaunchKernelGGL((k_strided<T, N, SM_FWD_SCALE, TBV, NTV>), grid, dim3(NTV), 0, s, a);
         else if (mode == SM_FWD_CGQ)
@@ -908,6 +1105,19 @@ template <> hipError_t launch_zinv<double>(int n, int mode, const ZinvArgs<doubl
     default: return hipErrorInvalidValue;
   }
 }
+template <typename T>
+hipError_t launch_zmid(int n, const ZmidArgs<T>& a, int64_t nrows, int nrhs, hipStream_t s) {
+  switch (n) {
+#define X(L) \
+  case L: return zmid_n<T, L>(a, nrows, nrhs, s);
+    WF_FOR_F32(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_zmid<float>(int, const ZmidArgs<float>&, int64_t, int, hipStream_t);
+template hipError_t launch_zmid<double>(int, const ZmidArgs<double>&, int64_t, int, hipStream_t);
+
 template <> hipError_t launch_zinv<float>(int n, int mode, const ZinvArgs<float>& a, int64_t nrows,
                                           int nrhs, hipStream_t s) {
   switch (n) {

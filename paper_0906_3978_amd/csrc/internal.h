@@ -126,7 +126,7 @@ struct SolveWork {
   int64_t vlen = 0;
   DevBuf b64, x64, r64, p64, q64, spec64;
   DevBuf x32, r32, p32, q32, spec32;
-  DevBuf bh64, u64, u32;  // split: C b (half spectrum), real scratch fields
+  DevBuf bh64, u64;  // split: C b (half spectrum), a real field per RHS
   DevBuf state, partials;
   CgState* st_host = nullptr;   // pinned mirror of the state array
   int st_cap = 0;
@@ -141,16 +141,17 @@ Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32, hip
 // Prior-split operator (C A C) on half-spectrum vectors (stride spec_total
 // complex per RHS).  ensure_split_fac builds c once per power spectrum.
 // split_passes: q = C A C p (mode SM_FWD_CGQ, with p.q and FIN_PQ) or
-// r = b_hat - C A C y (SM_FWD_RES, FP64, with ||r||^2 and FIN_RES); `u` is a
-// real scratch field per RHS.  split_rhs: b_hat = C b.  split_solution:
-// s = C y into real fields.
+// r = b_hat - C A C y (SM_FWD_RES, FP64, with ||r||^2 and FIN_RES), through
+// the half spectrum `work`.  With rdir (and xdir) the CG direction update
+// p = r + beta p (and the pending x += alpha p) happens in the first pass.  split_rhs: b_hat = C b.  split_solution: s = C y
+// into real fields.
 Status ensure_split_fac(const Allocator& al, OperatorData& od, hipStream_t s);
 Status alloc_split_fac(const Allocator& al, OperatorData& od);
 Status build_split_fac(OperatorData& od, hipStream_t s);
 template <typename T>
-Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* work, T* u, T* out,
+Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* work, T* out,
                     const double* bh, CgState* st, double* partials, int nrhs, int skip,
-                    hipStream_t s);
+                    hipStream_t s, const T* rdir = nullptr, T* xdir = nullptr);
 Status split_rhs(const OperatorData& od, const double* b, cplx<double>* work, double* bh,
                  int nrhs, hipStream_t s);
 Status split_solution(const OperatorData& od, const double* yh, cplx<double>* work, double* s_out,

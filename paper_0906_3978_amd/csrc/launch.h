@@ -10,7 +10,7 @@ namespace wf {
 
 // ---- z-axis passes (contiguous rows, real <-> half spectrum) --------------
 enum ZinMode : int { ZIN_REAL = 0, ZIN_CGP = 1, ZIN_I64 = 2 };
-enum ZoutMode : int { ZOUT_REAL = 0, ZOUT_CGQ = 1, ZOUT_RES = 2, ZOUT_APPLY = 3, ZOUT_W = 4 };
+enum ZoutMode : int { ZOUT_REAL = 0, ZOUT_CGQ = 1, ZOUT_RES = 2, ZOUT_APPLY = 3 };
 
 template <typename T> struct ZfwdArgs {
   const T* in;              // ZIN_REAL: rows; ZIN_CGP: r
@@ -35,13 +35,25 @@ template <typename T> struct ZinvArgs {
   int64_t rhs_out;
   const T* aux;             // CGQ: p; RES: x; APPLY: v
   int64_t rhs_aux;
-  const T* w;               // mask (shared by all RHS); W: out = nbar w * (inverse FFT)
+  const T* w;               // mask (shared by all RHS)
   const double* bvec;       // RES: b
   int64_t rhs_b;
   double scale;             // REAL: output scale
   double* partials;         // per RHS: gridDim.x doubles
   const cplx<T>* tw;
   CgState* st;
+  int32_t skip;             // SKIP_*
+};
+
+// z middle pass of the prior-split operator: spectrum -> real rows -> times
+// nbar w (nbar from the RHS state) -> spectrum, in place
+template <typename T> struct ZmidArgs {
+  cplx<T>* spec_main;       // [row][N/2]
+  cplx<T>* spec_nyq;        // [row]
+  int64_t rhs_main, rhs_nyq;
+  const T* w;               // mask (shared by all RHS)
+  const cplx<T>* tw;
+  const CgState* st;        // required
   int32_t skip;             // SKIP_*
 };
 
@@ -54,9 +66,11 @@ template <typename T> struct ZinvArgs {
 // D = 2 for 0 < kz < N/2 and 1 on the kz = 0 and kz = N/2 planes: the half
 // spectrum stores each conjugate pair once, and carrying sqrt(D) in the vectors
 // makes their plain dot products the full-spectrum inner products.
+// INV_DIR is INV_SCALE of the CG direction, formed on the way in: `in` is r,
+// the pending x += alpha p is applied and p = r + beta p written back (Seg p, x).
 enum StrMode : int {
   SM_FWD = 0, SM_INV = 1, SM_FWD_LAM_INV = 2, SM_FWD_CROP = 3,
-  SM_INV_SCALE = 4, SM_FWD_SCALE = 5, SM_FWD_CGQ = 6, SM_FWD_RES = 7
+  SM_INV_SCALE = 4, SM_FWD_SCALE = 5, SM_FWD_CGQ = 6, SM_FWD_RES = 7, SM_INV_DIR = 8
 };
 
 template <typename T> struct Seg {
@@ -70,6 +84,8 @@ template <typename T> struct Seg {
   int32_t lam_y_outer, lam_kz, pad0, pad1;
   const cplx<T>* aux;       // split CGQ / RES: vector at the output's positions
   const cplx<double>* bvec; // split RES: b at the output's positions
+  cplx<T>* p;               // split INV_DIR: direction and iterate at the input's positions
+  cplx<T>* x;
 };
 
 template <typename T> struct StrArgs {
@@ -79,7 +95,8 @@ template <typename T> struct StrArgs {
   const cplx<T>* tw;
   const CgState* st;        // may be null
   int32_t skip;             // SKIP_* (needs st)
-  const T* fac;             // split modes: c over (|my|, |mx|, kz), [|my|][|mx|][kz]
+  const T* fac;             // split modes: c over (|my|, |mx|, kz), [|my|][|mx|][kz] with
+                            // the kz rows padded to an even length
   double in_scale;          // SM_INV_SCALE: 1 / M
   double* partials;         // SM_FWD_CGQ / SM_FWD_RES: per RHS, one per block
 };
@@ -95,6 +112,8 @@ template <typename T> hipError_t launch_zinv(int n, int mode, const ZinvArgs<T>&
                                              int64_t nrows, int nrhs, hipStream_t s);
 template <typename T> hipError_t launch_strided(int n, int mode, const StrArgs<T>& a,
                                                 int nrhs, hipStream_t s);
+template <typename T> hipError_t launch_zmid(int n, const ZmidArgs<T>& a, int64_t nrows, int nrhs,
+                                             hipStream_t s);
 
 // Sums the block partials of one reduction (nparts per RHS, fixed order) and
 // updates the CG state: FIN_PQ -> alpha (or breakdown), FIN_RR -> iteration
@@ -162,7 +181,7 @@ hipError_t launch_xlam_rows(int n, const double* lam, double* rows64, float* row
                             hipStream_t s);
 // Prior-split factor c = Lambda^(-1/2) over (|my|, |mx|, kz) in [0, n/2]^3 from
 // the |m|^2 table (which carries 1/M), c at |m|^2 = 1 standing in for the
-// monopole; FP64 and FP32 copies.
+// monopole; rows of kz padded to an even length; FP64 and FP32 copies.
 int64_t split_fac_elems(int n);
 hipError_t launch_split_fac(int n, const double* lam, double m_cells, double* fac64, float* fac32,
                             hipStream_t s);

@@ -359,7 +359,6 @@ void wf_server::retire(const std::shared_ptr<Job>& j, bool ok) {
   j->od.fac32.release();
   j->sw.bh64.release();
   j->sw.u64.release();
-  j->sw.u32.release();
   j->od.tw64.release();
   j->od.tw32.release();
   j->dw.grid.release();
@@ -372,7 +371,7 @@ void wf_server::retire(const std::shared_ptr<Job>& j, bool ok) {
   j->scal.release();
   j->staging.release();
   for (DevBuf* b : {&j->sw.b64, &j->sw.x64, &j->sw.r64, &j->sw.p64, &j->sw.q64, &j->sw.spec64,
-                    &j->sw.x32, &j->sw.r32, &j->sw.p32, &j->sw.q32, &j->sw.spec32, &j->sw.bh64, &j->sw.u64, &j->sw.u32, &j->sw.state,
+                    &j->sw.x32, &j->sw.r32, &j->sw.p32, &j->sw.q32, &j->sw.spec32, &j->sw.bh64, &j->sw.u64, &j->sw.state,
                     &j->sw.partials})
     b->release();
   std::vector<double>().swap(j->w);
@@ -417,7 +416,7 @@ void wf_server::run() {
                           &j->od.tw32, &j->dw.grid, &j->dw.fine_spec, &j->dw.spec_y, &j->dw.spec_c,
                           &j->dw.tw_fine, &j->xyz_d, &j->nobs, &j->scal, &j->staging, &j->sw.b64,
                           &j->sw.x64, &j->sw.r64, &j->sw.p64, &j->sw.q64, &j->sw.spec64, &j->sw.x32,
-                          &j->sw.r32, &j->sw.p32, &j->sw.q32, &j->sw.spec32, &j->sw.bh64, &j->sw.u64, &j->sw.u32, &j->sw.state,
+                          &j->sw.r32, &j->sw.p32, &j->sw.q32, &j->sw.spec32, &j->sw.bh64, &j->sw.u64, &j->sw.state,
                           &j->sw.partials})
           b->release();
         std::lock_guard<std::mutex> g(mu);

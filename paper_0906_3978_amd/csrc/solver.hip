@@ -64,19 +64,13 @@ Status cg_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hi
 
 // One CG iteration of the prior-split system; vectors are half spectra.
 template <typename T>
-Status split_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, T* u, int nr,
-                       hipStream_t s) {
+Status split_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hipStream_t s) {
   CgState* st = sw.state.as<CgState>();
   double* parts = sw.partials.as<double>();
   const int64_t vl = sw.vlen;
   const bool f64 = sizeof(T) == 8;
-  {
-    // r, p, x in; p, x out
-    ProfScope ps(od.prof, f64 ? WF_PROF_SDIR_F64 : WF_PROF_SDIR_F32, 5.0 * sizeof(T) * vl * nr, s);
-    WF_HIP(launch_cg_dir<T>(v.x, v.p, v.r, vl, vl, st, nr, s));
-  }
-  WF_TRY(split_passes<T>(od, SM_FWD_CGQ, v.p, v.spec, u, v.q, nullptr, st, parts, nr, SKIP_DONE,
-                         s));
+  WF_TRY(split_passes<T>(od, SM_FWD_CGQ, v.p, v.spec, v.q, nullptr, st, parts, nr, SKIP_DONE, s,
+                         v.r, v.x));
   {
     ProfScope ps(od.prof, f64 ? WF_PROF_UPDATE_F64 : WF_PROF_UPDATE_F32, 3.0 * sizeof(T) * vl * nr,
                  s);
@@ -89,10 +83,7 @@ Status split_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, T* u, i
 template <typename T>
 Status any_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hipStream_t s) {
   if (!sw.split) return cg_iteration<T>(od, sw, v, nr, s);
-  T* u;
-  if constexpr (sizeof(T) == 8) u = sw.u64.as<double>();
-  else u = sw.u32.as<float>();
-  return split_iteration<T>(od, sw, v, u, nr, s);
+  return split_iteration<T>(od, sw, v, nr, s);
 }
 
 // Runs CG iterations in chunks of `check` until every RHS is done.
@@ -232,8 +223,8 @@ Status solve_update(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s
                          nr, s));
   if (sw.split) {
     WF_TRY(split_passes<double>(od, SM_FWD_RES, sw.x64.as<double>(), sw.spec64.as<double2>(),
-                                sw.u64.as<double>(), sw.r64.as<double>(), sw.bh64.as<double>(), st,
-                                parts, nr, SKIP_UNLESS_UPDATE, s));
+                                sw.r64.as<double>(), sw.bh64.as<double>(), st, parts, nr,
+                                SKIP_UNLESS_UPDATE, s));
   } else {
     WF_TRY(operator_passes<double>(od, ZIN_REAL, sw.x64.as<double>(), nullptr, nullptr,
                                    sw.spec64.as<double2>(), ZOUT_RES, sw.r64.as<double>(),
@@ -483,7 +474,7 @@ size_t footprint_bytes(int n, int ss, wf_precision prec, int nrhs, bool split) {
   if (split) op += 12.0 * (double)split_fac_elems(n);
   double per = 8.0 * M + 16.0 * V + 16.0 * ST;              // b, x, r, spec64
   per += prec == WF_FP64 ? 16.0 * V : 16.0 * V + 8.0 * ST;  // p, q | 4 FP32 vectors, spec32
-  if (split) per += 8.0 * V + 8.0 * M + (prec == WF_MIXED ? 4.0 * M : 0.0);  // C b, scratch
+  if (split) per += 8.0 * V + 8.0 * M;  // C b, a real field
   const int nf = ss * n;
   double dep = 8.0 * (double)nf * nf * nf + 8.0 * M;  // integer grid, n_obs
   if (ss == 2)
