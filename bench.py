@@ -28,10 +28,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-# Outer (FP64) residual tolerance of the refinement; chosen so that the error
-# against the FP64 oracle solution stays below 1e-6 (the error is a few
-# hundred times the residual on these problems).
-DEFAULT_TOL = 2e-9
+# Outer (FP64) residual tolerance of the refinement per preconditioning,
+# chosen so that the error against the FP64 oracle solution stays below 1e-6.
+# Plain CG stops on ||b - A s|| / ||b||, whose error is ~100x the residual on
+# these problems; the prior-split CG stops on ||C (b - A s)|| / ||C b||.
+TOLERANCES = {"none": 2e-9, "prior": 2e-9}
+DEFAULT_TOL = TOLERANCES["none"]
 KERNEL_SOURCES = ["paper_0906_3978_amd/csrc/fftpass.hip", "paper_0906_3978_amd/csrc/kernels.hip",
                   "paper_0906_3978_amd/csrc/fft.h",
                   "paper_0906_3978_amd/csrc/common.h"]
@@ -61,29 +63,33 @@ def make_inputs(name, n_override=None):
     return wl, ptab, w, cat
 
 
-def cpu_baseline(wl, ptab, w, n_gal, iters_fp64, sample_iters=3):
-    """The oracle's plain CG on the same system, timed on the host cores over a
-    few iterations and scaled to a whole FP64 solve of `iters_fp64`
-    iterations (the oracle's algorithm)."""
+def cpu_baseline(wl, ptab, w, n_gal, iters_fp64, precond="none", sample_iters=3):
+    """The oracle's CG on the same system (plain, or on the prior-split system
+    for precond="prior"), timed on the host cores over a few iterations and
+    scaled to a whole FP64 solve of `iters_fp64` iterations."""
     from threadpoolctl import threadpool_limits
     from oracle import wiener as ow
     nbar = ow.mean_density(n_gal, w)
     system = ow.System(wl.n, wl.box, w, ptab, nbar)
     rng = np.random.Generator(np.random.PCG64(7))
     b = np.where(w > 0, rng.standard_normal(w.shape), 0.0)
+    solve = ow.split_cg if precond == "prior" else ow.cg
+    name = "prior-split CG" if precond == "prior" else "plain-CG"
     with threadpool_limits(1):
-        ow.cg(system, b, 0.0, 1)  # warm the FFT plan cache
-        t = time.perf_counter()
-        ow.cg(system, b, 0.0, sample_iters)
-        dt = (time.perf_counter() - t) / sample_iters
+        solve(system, b, 0.0, 1)  # warm the FFT plan cache
+        t0 = time.perf_counter()
+        solve(system, b, 0.0, 0)  # the set-up and final residual, without iterations
+        t1 = time.perf_counter()
+        solve(system, b, 0.0, sample_iters)
+        dt = (time.perf_counter() - t1 - (t1 - t0)) / sample_iters
     per_solve = dt * iters_fp64
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{sample_iters} plain-CG iterations of the FP64 numpy oracle on the "
+            "sample": (f"{sample_iters} {name} iterations of the FP64 numpy oracle on the "
                        f"{wl.n}^3 system ({dt:.2f} s/iteration, one core) scaled to the "
                        f"{iters_fp64} iterations of one FP64 solve; gridding not included")}
 
 
-def serve(n_req, tol, seed=5000):
+def serve(n_req, tol, precond="prior", seed=5000):
     """Serving stream: requests drawn by synth.serving_request (grids 64..384,
     random caps, radial scales, spectrum amplitudes and catalogue sizes).
     Phase A serves them one at a time (isolated capacity, and the reference
@@ -103,7 +109,7 @@ def serve(n_req, tol, seed=5000):
     log(f"[serve] generated {n_req} requests ({time.perf_counter() - t:.1f} s), grids "
         f"{sorted(set(r[0].n for r in reqs))}")
     budget = 96 << 30
-    kw = dict(precision="mixed", tol=tol, max_iter=100000)
+    kw = dict(precision="mixed", tol=tol, max_iter=100000, precond=precond)
 
     def submit(srv, r):
         wl, w, ptab, xyz = r
@@ -143,7 +149,7 @@ def serve(n_req, tol, seed=5000):
     return res
 
 
-def batch_run(nrhs, tol):
+def batch_run(nrhs, tol, precond="prior"):
     """Multi-RHS batch: nrhs lognormal-Poisson catalogues of 1e6 galaxies on a
     shared 256^3 / 500 Mpc grid, mask and BBKS prior, CIC 2x supersampled,
     solved in one mixed-precision batch (every pass one launch for all RHS);
@@ -164,7 +170,7 @@ def batch_run(nrhs, tol):
     ctx.set_grid(wl.n, wl.box)
     ctx.set_mask(w)
     ctx.set_power(ptab)
-    kw = dict(precision="mixed", tol=tol, max_iter=100000)
+    kw = dict(precision="mixed", tol=tol, max_iter=100000, precond=precond)
     ctx.solve_batch(cats[:2], "cic", 2, **kw)  # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -213,11 +219,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="bbks512")
     ap.add_argument("--n", type=int, default=None, help="override the grid size (testing)")
-    ap.add_argument("--tol", type=float, default=DEFAULT_TOL)
+    ap.add_argument("--tol", type=float, default=None,
+                    help="outer residual tolerance (default: per --precond)")
     ap.add_argument("--inner-tol", type=float, default=0.0)
-    ap.add_argument("--precond", choices=["none", "prior"], default="none",
-                    help="CG preconditioning: none (plain CG on A) or prior (the prior-split "
-                         "system C A C)")
+    ap.add_argument("--precond", choices=["none", "prior"], default="prior",
+                    help="CG preconditioning: prior (the prior-split system C A C) or none "
+                         "(plain CG on A)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the comparison solve with plain (unpreconditioned) CG")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -229,6 +238,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="also run the multi-RHS batch: this many 256^3 catalogues in one solve")
     args = ap.parse_args()
+    if args.tol is None:
+        args.tol = TOLERANCES[args.precond]
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build measures one GPU: the Wiener solve of one grid "
@@ -316,8 +327,11 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                     "traffic": traffic_for(dom, bpl), "algorithmic_bytes_per_launch": bpl,
                     "avg_launch_us": round(avg_s * 1e6, 2)}
-        # whole-iteration figure: the five sweeps + update of the FP32 inner CG
-        it_keys = ["zfwd_f32", "yfwd_f32", "xlam_f32", "yinv_f32", "zinv_f32", "update_f32"]
+        # whole-iteration figure: the sweeps + update of the FP32 inner CG
+        if args.precond == "prior":
+            it_keys = ["sxinv_f32", "yinv_f32", "szw_f32", "yfwd_f32", "sxfwd_f32", "update_f32"]
+        else:
+            it_keys = ["zfwd_f32", "yfwd_f32", "xlam_f32", "yinv_f32", "zinv_f32", "update_f32"]
         if all(k in prof for k in it_keys):
             it_ms = sum(prof[k]["ms"] / prof[k]["launches"] for k in it_keys)
             it_b = sum(prof[k]["bytes"] / prof[k]["launches"] for k in it_keys)
@@ -332,7 +346,8 @@ def main():
         ctx.deposit(wl.scheme, wl.supersample)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, inf64 = ctx.solve(out=out, precision="fp64", tol=args.tol, max_iter=100000)
+        _, inf64 = ctx.solve(out=out, precision="fp64", tol=args.tol, max_iter=100000,
+                             precond=args.precond)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t
         fp64 = {"solve_s": round(t64, 4), "solves_per_s_solve_only": round(1.0 / t64, 4),
@@ -341,15 +356,31 @@ def main():
                 "speedup_mixed_over_fp64_solve": round(t64 / (info.time_ms * 1e-3), 3)}
         log(f"[bench] fp64 solve {t64:.3f} s iters={inf64.iters_total}")
 
+    plain = None
+    if not args.no_plain and args.precond != "none":
+        ctx.set_galaxies(xyz_d)
+        ctx.deposit(wl.scheme, wl.supersample)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, infp = ctx.solve(out=out, precision="mixed", tol=TOLERANCES["none"], max_iter=100000,
+                            precond="none")
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        plain = {"precond": "none", "tol_outer": TOLERANCES["none"], "solve_s": round(tp, 4),
+                 "iters": infp.iters_total, "outer_steps": infp.outer_steps,
+                 "rel_res_true": infp.rel_res_true,
+                 "speedup_of_prior_split": round(tp / (info.time_ms * 1e-3), 3)}
+        log(f"[bench] plain mixed solve {tp:.3f} s iters={infp.iters_total}")
+
     cpu = None
     if not args.no_cpu_baseline:
         iters_ref = fp64["iters"] if fp64 else info.iters_total
         t = time.perf_counter()
-        cpu = cpu_baseline(wl, ptab, w, len(cat.xyz), iters_ref)
+        cpu = cpu_baseline(wl, ptab, w, len(cat.xyz), iters_ref, args.precond)
         log(f"[bench] cpu baseline {cpu['value']:.3e} solves/s ({time.perf_counter() - t:.1f} s)")
 
-    serving = serve(args.serve, args.tol) if args.serve else None
-    batch = batch_run(args.batch, args.tol) if args.batch else None
+    serving = serve(args.serve, args.tol, args.precond) if args.serve else None
+    batch = batch_run(args.batch, args.tol, args.precond) if args.batch else None
 
     lat_ms = sorted(1e3 * x for x in lat)
     res = {
@@ -368,16 +399,19 @@ def main():
         "config": {"workload": f"{wl.name}: {n}^3 grid, {wl.box:.0f} Mpc box, BBKS prior, "
                                f"60 deg cap x exp(-r/150 Mpc), {len(cat.xyz)} lognormal-Poisson "
                                f"galaxies, {wl.scheme.upper()} deposit 2x supersampled, "
-                               f"mixed-precision CG to FP64 residual {args.tol:g}",
+                               f"mixed-precision "
+                               f"{'prior-split ' if args.precond == 'prior' else ''}CG to "
+                               f"FP64 residual {args.tol:g}",
                    "n": n, "box_mpc": wl.box, "n_gal": int(len(cat.xyz)),
                    "scheme": wl.scheme, "supersample": wl.supersample,
-                   "tol_outer": args.tol, "iters": info.iters_total,
+                   "precond": args.precond, "tol_outer": args.tol, "iters": info.iters_total,
                    "outer_steps": info.outer_steps, "rel_res_true": info.rel_res_true},
         "latency_ms": {"p50": round(lat_ms[len(lat_ms) // 2], 3),
                        "p99": round(lat_ms[min(len(lat_ms) - 1, math.ceil(0.99 * len(lat_ms)) - 1)], 3)},
         "roofline": roofline,
         "kernels": per_kernel,
         "fp64": fp64,
+        "plain_cg": plain,
         "cpu_baseline": cpu,
         "serving": serving,
         "batch": batch,

@@ -6,6 +6,11 @@ the oracle's own deposit and low-pass.  It is stored as float32 (the
 comparison it serves is at the 1e-6 level) with a JSON sidecar.
 
     python tests/golden/make_reference.py bbks512 OUTDIR [--workers 8]
+
+With --sample-from FULL.npy it instead reads such a stored reference and
+writes every --stride-th cell along each axis (cells [::s, ::s, ::s]) to
+OUTDIR/<workload>_n<n>_x_s<s>.npy: the sampled outputs a full-size GPU test
+compares against.
 """
 import argparse
 import json
@@ -30,9 +35,19 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--workers", type=int, default=os.cpu_count())
+    ap.add_argument("--sample-from", default=None)
+    ap.add_argument("--stride", type=int, default=8)
     a = ap.parse_args()
     os.makedirs(a.outdir, exist_ok=True)
     wl = synth.workload(a.workload, n=a.n)
+    if a.sample_from:
+        full = np.load(a.sample_from, mmap_mode="r")
+        st = a.stride
+        sample = np.ascontiguousarray(full[::st, ::st, ::st], dtype=np.float32)
+        out = os.path.join(a.outdir, f"{wl.name}_n{wl.n}_x_s{st}.npy")
+        np.save(out, sample)
+        print("wrote", out, sample.shape, flush=True)
+        return
     t0 = time.time()
     ptab = wl.ptab()
     w = wl.mask()
