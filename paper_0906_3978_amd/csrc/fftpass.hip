@@ -627,6 +627,20 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
     }
   }
   load_twiddles<T, N, NT>(twl, a.tw);
+  // split CGQ / RES: the aux vector at the output's positions, requested
+  // before the FFT so that the loads complete under it (VEC tiles)
+  R avp[(REDUCE && VEC) ? PER : 1];
+  if constexpr (REDUCE && VEC) {
+    const int64_t ob = rhs * s.out_rhs + outer * s.out_outer + b0 * s.out_batch;
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+      const int q = threadIdx.x + c * NT;
+      if (ITEMS % NT == 0 || q < ITEMS) {
+        const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+        avp[c] = ld16x<NTA>(reinterpret_cast<const T*>(s.aux + ob + i * s.out_axis + b));
+      }
+    }
+  }
   if constexpr (MODE == SM_FWD_LAM_INV) {
     // Lambda of the elements this thread holds between the forward and the
     // inverse transform, read from the column's row of the x-pass table
@@ -706,7 +720,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           const int64_t off = ob + i * s.out_axis + b;
           const R v = *reinterpret_cast<const R*>(lds + q * CW);
           R av{};
-          if constexpr (REDUCE) av = ld16x<NTA>(reinterpret_cast<const T*>(s.aux + off));
+          if constexpr (REDUCE) av = avp[c];
           T f[CW];
           int kz[CW];
           bool dc[CW];
