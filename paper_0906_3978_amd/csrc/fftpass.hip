@@ -418,6 +418,22 @@ __global__ __launch_bounds__(NT) void k_zmid(ZmidArgs<T> a) {
 // ---------------------------------------------------------------------------
 // strided passes (y or x axis)
 // ---------------------------------------------------------------------------
+// Layout of the prior-split CG vectors (half spectra touched only by the x
+// passes and by pointwise kernels): tile-contiguous in the order the x pass
+// reads them.  Column c of outer row o (the columns of an outer row are kz
+// for the main part and y for the kz = N/2 plane), x index i:
+//   ((o * ncols / TV + c / TV) * N + i) * TV + c % TV,
+// TV = the narrower strided tile of the two precisions, so FP32 and FP64
+// vectors share the layout.
+template <int N> constexpr int vec_tile() {
+  return str_tb<float, N>() < str_tb<double, N>() ? str_tb<float, N>() : str_tb<double, N>();
+}
+template <int N>
+__device__ __forceinline__ int64_t vec_off(int outer, int ncols, int c, int i) {
+  constexpr int TV = vec_tile<N>();
+  return ((int64_t)(outer * (ncols / TV) + c / TV) * N + i) * TV + c % TV;
+}
+
 // Row stride of the prior-split factor table [|my|][|mx|][kz] (kz < N/2 + 1,
 // padded to an even count so that kz pairs load as one aligned vector).
 template <int N> constexpr int split_row() { return (N / 2 + 2) & ~1; }
@@ -520,7 +536,11 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
         const int q = threadIdx.x + c * NT;
         if (ITEMS % NT == 0 || q < ITEMS) {
           const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-          buf[c] = ld16x<NTA>(reinterpret_cast<const T*>(in + i * s.in_axis + b));
+          if constexpr (SCALE_IN)
+            buf[c] = ld16x<NTA>(reinterpret_cast<const T*>(
+                s.in + rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i)));
+          else
+            buf[c] = ld16x<NTA>(reinterpret_cast<const T*>(in + i * s.in_axis + b));
         }
       }
       if constexpr (MODE == SM_INV_DIR) {
@@ -528,17 +548,17 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
         const CgState* cs = a.st + rhs;
         const bool first = cs->first != 0, pending = cs->pending != 0;
         const T alpha = (T)cs->alpha, beta = (T)cs->beta;
-        const int64_t vo = rhs * s.in_rhs + outer * s.in_outer + b0 * s.in_batch;
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
           const int q = threadIdx.x + c * NT;
           if (ITEMS % NT == 0 || q < ITEMS) {
             const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-            T* pp = reinterpret_cast<T*>(s.p + vo + i * s.in_axis + b);
+            const int64_t vo = rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i);
+            T* pp = reinterpret_cast<T*>(s.p + vo);
             if (!first) {
               const R pv = ld16x<NTA>(pp);
               if (pending) {
-                T* xp = reinterpret_cast<T*>(s.x + vo + i * s.in_axis + b);
+                T* xp = reinterpret_cast<T*>(s.x + vo);
                 st16x<NTA>(xp, ld16x<NTA>(xp) + alpha * pv);
               }
               buf[c] += beta * pv;
@@ -570,10 +590,12 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
     } else {
       for (int e = threadIdx.x; e < TB * N; e += NT) {
         const int b = e % TB, i = e / TB;
-        V v = in[i * s.in_axis + b];
+        V v;
+        if constexpr (SCALE_IN) v = s.in[rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i)];
+        else v = in[i * s.in_axis + b];
         if constexpr (MODE == SM_INV_DIR) {
           const CgState* cs = a.st + rhs;
-          const int64_t o = rhs * s.in_rhs + outer * s.in_outer + b0 * s.in_batch + i * s.in_axis + b;
+          const int64_t o = rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i);
           if (!cs->first) {
             const V pv = s.p[o];
             if (cs->pending) {
@@ -631,13 +653,13 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   // before the FFT so that the loads complete under it (VEC tiles)
   R avp[(REDUCE && VEC) ? PER : 1];
   if constexpr (REDUCE && VEC) {
-    const int64_t ob = rhs * s.out_rhs + outer * s.out_outer + b0 * s.out_batch;
 #pragma unroll
     for (int c = 0; c < PER; ++c) {
       const int q = threadIdx.x + c * NT;
       if (ITEMS % NT == 0 || q < ITEMS) {
         const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-        avp[c] = ld16x<NTA>(reinterpret_cast<const T*>(s.aux + ob + i * s.out_axis + b));
+        avp[c] = ld16x<NTA>(reinterpret_cast<const T*>(
+            s.aux + rhs * s.out_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i)));
       }
     }
   }
@@ -710,14 +732,15 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   } else if constexpr (SPLIT_OUT) {
     // x-pass segments only (the batch is contiguous)
     double acc = 0.0;
-    const int64_t ob = rhs * s.out_rhs + outer * s.out_outer + b0 * s.out_batch;
+    const int64_t ob = rhs * s.out_rhs;
+    const int ncols = s.n_btiles * TB;
     if constexpr (VEC) {
 #pragma unroll
       for (int c = 0; c < PER; ++c) {
         const int q = threadIdx.x + c * NT;
         if (ITEMS % NT == 0 || q < ITEMS) {
           const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-          const int64_t off = ob + i * s.out_axis + b;
+          const int64_t off = ob + vec_off<N>(outer, ncols, b0 + b, i);
           const R v = *reinterpret_cast<const R*>(lds + q * CW);
           R av{};
           if constexpr (REDUCE) av = avp[c];
@@ -741,7 +764,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
     } else {
       for (int e = threadIdx.x; e < TB * N; e += NT) {
         const int b = e % TB, i = e / TB;
-        const int64_t off = ob + i * s.out_axis + b;
+        const int64_t off = ob + vec_off<N>(outer, ncols, b0 + b, i);
         T f;
         int kz;
         bool dc;
