@@ -231,8 +231,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=0,
-                    help="profiling run: one deposit, this many mixed iterations and a 1 GiB "
-                         "device copy (the reference for scaling HBM counters), then exit")
+                    help="profiling run: one deposit, this many mixed iterations (of --precond) "
+                         "and a 1 GiB device copy (the reference for scaling HBM counters), "
+                         "then exit")
     ap.add_argument("--serve", type=int, default=0,
                     help="also run a serving stream of this many requests")
     ap.add_argument("--batch", type=int, default=0,
@@ -270,7 +271,7 @@ def main():
         ctx.set_galaxies(xyz_d)
         ctx.deposit(wl.scheme, wl.supersample)
         _, info = ctx.solve(out=out, precision="mixed", tol=0.0, max_iter=args.profile_iters,
-                            allow=(0, 5))
+                            allow=(0, 5), precond=args.precond)
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
