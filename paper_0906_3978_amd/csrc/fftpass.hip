@@ -434,9 +434,17 @@ __device__ __forceinline__ int64_t vec_off(int outer, int ncols, int c, int i) {
   return ((int64_t)(outer * (ncols / TV) + c / TV) * N + i) * TV + c % TV;
 }
 
-// Row stride of the prior-split factor table [|my|][|mx|][kz] (kz < N/2 + 1,
-// padded to an even count so that kz pairs load as one aligned vector).
-template <int N> constexpr int split_row() { return (N / 2 + 2) & ~1; }
+// Prior-split factor table: c over (|my|, |mx|, kz) in [0, N/2]^3, stored in
+// blocks of FB consecutive kz: [|my|][kz / FB][|mx|][kz % FB].  An x-pass
+// tile (one |my|, up to FB consecutive kz, every x) then reads one
+// contiguous block, and kz pairs load as one aligned vector.
+constexpr int FB = 16;
+template <int N> constexpr int split_kzb() { return (N / 2 + FB) / FB; }  // kz blocks
+template <int N>
+__device__ __forceinline__ int64_t fac_off(int my, int mx, int kz) {
+  constexpr int H = N / 2 + 1;
+  return ((int64_t)(my * split_kzb<N>() + kz / FB) * H + mx) * FB + kz % FB;
+}
 
 // Prior-split factors c of the CW elements at x index i, columns cb..cb+CW-1
 // of an x-pass segment (its fields give each column's |my| and kz), with the
@@ -444,13 +452,12 @@ template <int N> constexpr int split_row() { return (N / 2 + 2) & ~1; }
 template <typename T, int N, int CW>
 __device__ __forceinline__ void split_facs(const T* __restrict__ fac, const Seg<T>& s, int outer,
                                            int cb, int i, T* f, int* kz, bool* dc) {
-  constexpr int H = N / 2 + 1, HP = split_row<N>();
   int mx = signed_m(i, N);
   mx = mx < 0 ? -mx : mx;
   if (s.lam_kz < 0) {  // columns are kz = cb + j of the row my = outer
     int my = signed_m(outer, N);
     my = my < 0 ? -my : my;
-    const T* row = fac + ((int64_t)my * H + mx) * HP + cb;
+    const T* row = fac + fac_off<N>(my, mx, cb);  // cb is even: a pair never leaves its block
     if constexpr (CW == 2 && sizeof(T) == 4) {
       const float2 v = *reinterpret_cast<const float2*>(row);
       f[0] = v.x;
@@ -470,7 +477,7 @@ __device__ __forceinline__ void split_facs(const T* __restrict__ fac, const Seg<
       int my = signed_m(cb + j, N);
       my = my < 0 ? -my : my;
       kz[j] = s.lam_kz;
-      f[j] = fac[((int64_t)my * H + mx) * HP + s.lam_kz];
+      f[j] = fac[fac_off<N>(my, mx, s.lam_kz)];
       dc[j] = false;
     }
   }
@@ -941,18 +948,22 @@ bool fft_length_supported(int n, bool fp64) {
 }
 
 int64_t split_fac_elems(int n) {
-  const int64_t h = n / 2 + 1, hp = (n / 2 + 2) & ~1;
-  return (n >= 8 && n % 2 == 0) ? h * h * hp : 0;
+  const int64_t h = n / 2 + 1, kzb = (n / 2 + FB) / FB;
+  return (n >= 8 && n % 2 == 0) ? h * kzb * h * FB : 0;
 }
 
-__global__ void k_split_fac(const double* __restrict__ lam, int h, int hp, double m_cells,
+// i = ((my * kzb + kb) * h + mx) * FB + kr, kz = kb * FB + kr
+__global__ void k_split_fac(const double* __restrict__ lam, int h, int kzb, double m_cells,
                             double* fac64, float* fac32) {
-  const int64_t total = (int64_t)h * h * hp;
+  const int64_t total = (int64_t)h * kzb * h * FB;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const int kz = (int)(i % hp);
-    const int64_t row = i / hp;
-    const int my = (int)(row / h), mx = (int)(row % h);
+    const int kr = (int)(i % FB);
+    const int64_t r1 = i / FB;
+    const int mx = (int)(r1 % h);
+    const int64_t r2 = r1 / h;
+    const int kb = (int)(r2 % kzb), my = (int)(r2 / kzb);
+    const int kz = kb * FB + kr;
     double c = 0.0;  // padding
     if (kz < h) {
       int64_t j = (int64_t)my * my + (int64_t)mx * mx + (int64_t)kz * kz;
@@ -969,8 +980,8 @@ hipError_t launch_split_fac(int n, const double* lam, double m_cells, double* fa
   const int64_t total = split_fac_elems(n);
   if (total <= 0) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_split_fac, dim3(blocks), dim3(256), 0, s, lam, n / 2 + 1, (n / 2 + 2) & ~1,
-                     m_cells, fac64, fac32);
+  hipLaunchKernelGGL(k_split_fac, dim3(blocks), dim3(256), 0, s, lam, n / 2 + 1,
+                     (n / 2 + FB) / FB, m_cells, fac64, fac32);
   return hipGetLastError();
 }
 

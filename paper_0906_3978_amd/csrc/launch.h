@@ -95,8 +95,8 @@ template <typename T> struct StrArgs {
   const cplx<T>* tw;
   const CgState* st;        // may be null
   int32_t skip;             // SKIP_* (needs st)
-  const T* fac;             // split modes: c over (|my|, |mx|, kz), [|my|][|mx|][kz] with
-                            // the kz rows padded to an even length
+  const T* fac;             // split modes: c over (|my|, |mx|, kz), in blocks of 16 kz:
+                            // [|my|][kz / 16][|mx|][kz % 16]
   double in_scale;          // SM_INV_SCALE: 1 / M
   double* partials;         // SM_FWD_CGQ / SM_FWD_RES: per RHS, one per block
 };
@@ -181,7 +181,7 @@ hipError_t launch_xlam_rows(int n, const double* lam, double* rows64, float* row
                             hipStream_t s);
 // Prior-split factor c = Lambda^(-1/2) over (|my|, |mx|, kz) in [0, n/2]^3 from
 // the |m|^2 table (which carries 1/M), c at |m|^2 = 1 standing in for the
-// monopole; rows of kz padded to an even length; FP64 and FP32 copies.
+// monopole; blocks of 16 consecutive kz; FP64 and FP32 copies.
 int64_t split_fac_elems(int n);
 hipError_t launch_split_fac(int n, const double* lam, double m_cells, double* fac64, float* fac32,
                             hipStream_t s);
