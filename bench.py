@@ -29,10 +29,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 # Outer (FP64) residual tolerance of the refinement per preconditioning,
-# chosen so that the error against the FP64 oracle solution stays below 1e-6.
-# Plain CG stops on ||b - A s|| / ||b||, whose error is ~100x the residual on
-# these problems; the prior-split CG stops on ||C (b - A s)|| / ||C b||.
-TOLERANCES = {"none": 2e-9, "prior": 2e-9}
+# chosen so that the error against the FP64 solution stays below 1e-6 with a
+# margin.  Plain CG stops on ||b - A s|| / ||b||, whose error is ~200x the
+# residual on the 512^3 workload (2e-9 -> 4.5e-7); the prior-split CG stops on
+# ||C (b - A s)|| / ||C b||, whose error is about the residual (3e-7 -> 2.2e-7).
+TOLERANCES = {"none": 2e-9, "prior": 3e-7}
 DEFAULT_TOL = TOLERANCES["none"]
 KERNEL_SOURCES = ["paper_0906_3978_amd/csrc/fftpass.hip", "paper_0906_3978_amd/csrc/kernels.hip",
                   "paper_0906_3978_amd/csrc/fft.h",
