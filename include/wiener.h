@@ -233,6 +233,55 @@ wf_status wf_solve_batch(wf_ctx* ctx, int32_t nrhs, const double* const* xyz,
                          double* const* s_out, wf_mem mem,
                          wf_solve_info* infos);
 
+/* ---- after the solve: redshift space, filters, comparators ------------- */
+/* Redshift-distortion factor of Sec. 3.3.3: the angle average
+ *   g(k) = <K D>_mu = int_0^1 (1 + beta mu^2)^2 / (1 + k^2 sigma^2 mu^2 / 2) dmu
+ * of the Kaiser factor times the Lorentzian damping, at k = (2 pi / L) sqrt(j)
+ * for j = 0 .. len - 1 (len <= 3 (n/2)^2 + 1; sigma in Mpc, e.g. the paper's
+ * 500 km/s / H0).  P^s = g P^r is the redshift-space prior, to be passed to
+ * wf_set_power.  Needs wf_set_grid.  Writes `out` (len doubles on `mem`). */
+wf_status wf_rsd_factor(wf_ctx* ctx, double beta, double sigma_mpc, double* out,
+                        int64_t len, wf_mem mem);
+
+typedef enum {
+  WF_FILTER_GAUSS = 0,       /* h = exp(-k^2 r_S^2 / 2): the Gaussian smoothing of
+                                eq:GAUSS with radius a = r_S [Mpc] */
+  WF_FILTER_RSD_DECONV = 1,  /* h = 1 / (b sqrt(g(k))): the deconvolution eq:DEC by
+                                the angle-averaged redshift operator and a constant
+                                bias, a = beta, b = sigma [Mpc], c = bias */
+  WF_FILTER_TABLE = 2        /* h = table[j] at k = (2 pi / L) sqrt(j),
+                                len = 3 (n/2)^2 + 1 */
+} wf_filter_kind;
+
+/* out = F^-1 diag(h(|k|)) F in on the context's grid (FP64, n^3 doubles each,
+ * on `mem`; they may be the same buffer).  Non-finite h: WF_EINVAL. */
+wf_status wf_fourier_filter(wf_ctx* ctx, int32_t kind, double a, double b, double c,
+                            const double* table, int64_t len, const double* in,
+                            double* out, wf_mem mem);
+
+/* Moments of an n^3 field over all cells, or over those with w > 0
+ * (masked != 0): out[0..4] = cell count, mean, variance, skewness, excess
+ * kurtosis (population moments).  Synchronises. */
+wf_status wf_field_moments(wf_ctx* ctx, const double* v, int32_t masked, double* out5,
+                           wf_mem mem);
+
+/* Quality measures of Sec. 4.1 between a reconstruction and a reference
+ * field (n^3 each, over all cells or those with w > 0): out[0] = the
+ * correlation coefficient r, out[1] = the Euclidean distance D_Euc,
+ * out[2] = the Kullback-Leibler distance D_KL of 1 + delta (NaN where some
+ * 1 + delta <= 0).  Synchronises. */
+wf_status wf_compare_fields(wf_ctx* ctx, const double* rec, const double* truth,
+                            int32_t masked, double* out3, wf_mem mem);
+
+/* Inverse-weighting comparator (Sec. 4, the first step of the IW scheme):
+ * every galaxy of wf_set_galaxies weighted by 1/w of its nearest target node,
+ * deposited with `scheme` on the supersample-times-finer grid and low-passed
+ * as in wf_deposit, then delta_IW = n_IW / nbar - 1 with nbar of eq:nmean.
+ * A galaxy on a node with w = 0: WF_EINVAL.  FP64 atomic sums: reproducible to
+ * rounding, not bit for bit.  Writes `out` (n^3 doubles on `mem`). */
+wf_status wf_inverse_weighting(wf_ctx* ctx, wf_scheme scheme, int32_t supersample,
+                               double* out, wf_mem mem);
+
 /* ---- live kernel timing ------------------------------------------------ */
 /* Kernel classes timed by the profiler: the five sweeps of one operator
  * application and the CG vector update, in FP32 (0..5) and FP64 (6..11),

@@ -112,6 +112,12 @@ SIGNATURES = {
                                  _I32, C.POINTER(SolveOpts), C.POINTER(C.c_void_p), C.c_int,
                                  C.POINTER(SolveInfo)]),
     "wf_footprint_bytes": (_SZ, [_I32, _I32, C.c_int, _I32]),
+    "wf_rsd_factor": (C.c_int, [_V, C.c_double, C.c_double, _P, C.c_int64, C.c_int]),
+    "wf_fourier_filter": (C.c_int, [_V, _I32, C.c_double, C.c_double, C.c_double, _P, C.c_int64,
+                                    _P, _P, C.c_int]),
+    "wf_field_moments": (C.c_int, [_V, _P, _I32, _P, C.c_int]),
+    "wf_compare_fields": (C.c_int, [_V, _P, _P, _I32, _P, C.c_int]),
+    "wf_inverse_weighting": (C.c_int, [_V, C.c_int, _I32, _P, C.c_int]),
     "wf_profile_enable": (C.c_int, [_V, _I32]),
     "wf_profile_read": (C.c_int, [_V, C.POINTER(Profile)]),
     "wf_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, _SZ, _I32, ALLOC_FN, FREE_FN, _V]),
@@ -301,6 +307,56 @@ class Context:
         out = np.empty((n, n, n // 2 + 1), dtype=np.complex128)
         self._check(self._L.wf_forward_spectrum(self._h, PRECISIONS[precision], _ptr(v)[0],
                                                 out.ctypes.data, WF_HOST))
+        return out
+
+    # ---- after the solve (redshift space, filters, comparators) ---------
+    def rsd_factor(self, beta, sigma_mpc, length=None):
+        """<K D>_mu at k = (2 pi / L) sqrt(j), j < length (default 3 (n/2)^2 + 1)."""
+        n = self.n
+        length = length or 3 * (n // 2) ** 2 + 1
+        out = np.empty(length, dtype=np.float64)
+        self._check(self._L.wf_rsd_factor(self._h, float(beta), float(sigma_mpc), out.ctypes.data,
+                                          length, WF_HOST))
+        return out
+
+    def fourier_filter(self, v, kind, a=0.0, b=0.0, c=1.0, table=None, out=None):
+        """F^-1 diag(h) F v; kind "gauss" (a = r_S), "rsd_deconv" (a = beta,
+        b = sigma, c = bias) or "table" (h by |m|^2)."""
+        kinds = {"gauss": 0, "rsd_deconv": 1, "table": 2}
+        p, mem = _ptr(v)
+        if out is None:
+            out = np.empty(v.shape, dtype=np.float64) if mem == WF_HOST else v.new_empty(v.shape)
+        tp, tl = (None, 0)
+        if table is not None:
+            table = _as_f64(table) if mem == WF_HOST else table
+            tp, tl = _ptr(table)[0], int(_numel(table))
+        self._check(self._L.wf_fourier_filter(self._h, kinds[kind], float(a), float(b), float(c),
+                                              tp, tl, p, _ptr(out)[0], mem))
+        return out
+
+    def field_moments(self, v, masked=False):
+        """(count, mean, variance, skewness, excess kurtosis) over all cells or w > 0."""
+        p, mem = _ptr(v)
+        out = np.empty(5, dtype=np.float64)
+        self._check(self._L.wf_field_moments(self._h, p, int(bool(masked)), out.ctypes.data, mem))
+        return tuple(float(x) for x in out)
+
+    def compare_fields(self, rec, truth, masked=False):
+        """(r, D_Euc, D_KL) between a reconstruction and a reference field."""
+        pr, mem = _ptr(rec)
+        pt, _ = _ptr(truth)
+        out = np.empty(3, dtype=np.float64)
+        self._check(self._L.wf_compare_fields(self._h, pr, pt, int(bool(masked)), out.ctypes.data,
+                                              mem))
+        return tuple(float(x) for x in out)
+
+    def inverse_weighting(self, scheme="cic", supersample=2, out=None):
+        """delta_IW from the galaxies of set_galaxies (1/w weights, deposit, low-pass)."""
+        n = self.n
+        if out is None:
+            out = np.empty((n, n, n), dtype=np.float64)
+        p, mem = _ptr(out)
+        self._check(self._L.wf_inverse_weighting(self._h, SCHEMES[scheme], int(supersample), p, mem))
         return out
 
     # ---- solves ---------------------------------------------------------

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwiener.so")
 
-SOURCES = ["fftpass.hip", "kernels.hip", "core.hip", "solver.hip", "api.hip", "server.hip"]
+SOURCES = ["fftpass.hip", "kernels.hip", "core.hip", "solver.hip", "api.hip", "server.hip",
+           "post.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("WF_OFFLOAD_ARCH", "gfx950")

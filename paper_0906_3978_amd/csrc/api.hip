@@ -533,6 +533,205 @@ wf_status wf_solve_batch(wf_ctx* c, int32_t nrhs, const double* const* xyz, cons
   return finish(c, s);
 }
 
+// ---- after the solve ---------------------------------------------------------
+
+wf_status wf_rsd_factor(wf_ctx* c, double beta, double sigma, double* out, int64_t len,
+                        wf_mem mem) {
+  if (!c || !out) return c ? finish(c, fail(WF_EINVAL, "null output")) : WF_EINVAL;
+  Status s = need(c->have_grid, "wf_set_grid first");
+  if (!s.ok()) return finish(c, s);
+  const Grid& g = c->od.g;
+  if (len <= 0 || len > g.lamlen) return finish(c, fail(WF_EINVAL, "len must be in [1, 3 (n/2)^2 + 1]"));
+  if (!std::isfinite(beta) || !(sigma >= 0.0) || !std::isfinite(sigma))
+    return finish(c, fail(WF_EINVAL, "beta must be finite and sigma >= 0"));
+  auto run = [&]() -> Status {
+    WF_TRY(set_device(c));
+    DevBuf tmp;
+    double* dst = out;
+    if (mem == WF_HOST) {
+      WF_TRY(tmp.ensure(c->al, (size_t)len * 8));
+      dst = tmp.as<double>();
+    }
+    const double dk = 2.0 * M_PI / g.box;
+    WF_HIP(launch_rsd_factor(dk * dk, beta, sigma, dst, len, c->stream));
+    if (mem == WF_HOST) WF_TRY(download(out, dst, (size_t)len * 8, WF_HOST, c->stream));
+    WF_HIP(hipStreamSynchronize(c->stream));
+    return {};
+  };
+  return finish(c, run());
+}
+
+wf_status wf_fourier_filter(wf_ctx* c, int32_t kind, double a, double b, double cc,
+                            const double* table, int64_t len, const double* in, double* out,
+                            wf_mem mem) {
+  if (!c || !in || !out) return c ? finish(c, fail(WF_EINVAL, "null field")) : WF_EINVAL;
+  Status s = need(c->have_grid, "wf_set_grid first");
+  if (!s.ok()) return finish(c, s);
+  const Grid& g = c->od.g;
+  if (kind == WF_FILTER_TABLE) {
+    if (!table || len != g.lamlen)
+      return finish(c, fail(WF_EINVAL, "table length must be 3 (n/2)^2 + 1 = " + std::to_string(g.lamlen)));
+  } else if (kind == WF_FILTER_GAUSS) {
+    if (!(a >= 0.0) || !std::isfinite(a)) return finish(c, fail(WF_EINVAL, "r_S must be >= 0"));
+  } else if (kind == WF_FILTER_RSD_DECONV) {
+    if (!std::isfinite(a) || !(b >= 0.0) || !std::isfinite(b) || !(cc > 0.0) || !std::isfinite(cc))
+      return finish(c, fail(WF_EINVAL, "need finite beta, sigma >= 0 and bias > 0"));
+  } else {
+    return finish(c, fail(WF_EINVAL, "unknown filter kind"));
+  }
+  auto run = [&]() -> Status {
+    WF_TRY(set_device(c));
+    DevBuf h, rows64, rows32, field, spec, tab;
+    WF_TRY(h.ensure(c->al, (size_t)g.lamlen * 8));
+    const double* tdev = nullptr;
+    if (kind == WF_FILTER_TABLE) {
+      if (mem == WF_HOST) {
+        WF_TRY(tab.ensure(c->al, (size_t)g.lamlen * 8));
+        WF_TRY(upload(tab.p, table, (size_t)g.lamlen * 8, WF_HOST, c->stream));
+        tdev = tab.as<double>();
+      } else {
+        tdev = table;
+      }
+    }
+    WF_TRY(clear_flag(c));
+    const double dk = 2.0 * M_PI / g.box;
+    WF_HIP(launch_filter_table(kind, dk * dk, a, b, cc, tdev, g.lamlen, 1.0 / (double)g.m,
+                               h.as<double>(), c->flag.as<int>(), c->stream));
+    int bad = 0;
+    WF_TRY(read_flag(c, &bad));
+    if (bad) return fail(WF_EINVAL, "the filter is not finite everywhere");
+    WF_TRY(rows64.ensure(c->al, (size_t)g.xlamlen * 8));
+    WF_TRY(rows32.ensure(c->al, (size_t)g.xlamlen * 4));
+    WF_HIP(launch_xlam_rows(g.n, h.as<double>(), rows64.as<double>(), rows32.as<float>(), c->stream));
+    rows32.release();
+    WF_TRY(spec.ensure(c->al, (size_t)g.spec_total * 16));
+    const double* src = in;
+    double* dst = out;
+    if (mem == WF_HOST) {
+      WF_TRY(field.ensure(c->al, (size_t)g.m * 8));
+      WF_TRY(upload(field.p, in, (size_t)g.m * 8, WF_HOST, c->stream));
+      src = dst = field.as<double>();
+    }
+    WF_TRY(filter_passes(c->od, rows64.as<double>(), src, spec.as<double2>(), dst, c->stream));
+    if (mem == WF_HOST) WF_TRY(download(out, dst, (size_t)g.m * 8, WF_HOST, c->stream));
+    WF_HIP(hipStreamSynchronize(c->stream));
+    return {};
+  };
+  return finish(c, run());
+}
+
+wf_status wf_field_moments(wf_ctx* c, const double* v, int32_t masked, double* out5, wf_mem mem) {
+  if (!c || !v || !out5) return c ? finish(c, fail(WF_EINVAL, "null argument")) : WF_EINVAL;
+  Status s = need(c->have_grid && (!masked || c->have_mask), "needs the grid (and mask)");
+  if (!s.ok()) return finish(c, s);
+  auto run = [&]() -> Status {
+    WF_TRY(set_device(c));
+    const Grid& g = c->od.g;
+    DevBuf field;
+    const double* src = v;
+    if (mem == WF_HOST) {
+      WF_TRY(field.ensure(c->al, (size_t)g.m * 8));
+      WF_TRY(upload(field.p, v, (size_t)g.m * 8, WF_HOST, c->stream));
+      src = field.as<double>();
+    }
+    double sm[5];
+    WF_TRY(field_sums(src, masked ? c->od.w64.as<double>() : nullptr, g.m, c->mpartials, c->al, sm,
+                      c->stream));
+    const double n = sm[0];
+    double res[5] = {n, NAN, NAN, NAN, NAN};
+    if (n > 0) {
+      const double mu = sm[1] / n;
+      const double e2 = sm[2] / n, e3 = sm[3] / n, e4 = sm[4] / n;
+      const double var = e2 - mu * mu;
+      const double m3 = e3 - 3 * mu * e2 + 2 * mu * mu * mu;
+      const double m4 = e4 - 4 * mu * e3 + 6 * mu * mu * e2 - 3 * mu * mu * mu * mu;
+      res[1] = mu;
+      res[2] = var;
+      if (var > 0) {
+        res[3] = m3 / std::pow(var, 1.5);
+        res[4] = m4 / (var * var) - 3.0;
+      }
+    }
+    for (int k = 0; k < 5; ++k) out5[k] = res[k];
+    return {};
+  };
+  return finish(c, run());
+}
+
+wf_status wf_compare_fields(wf_ctx* c, const double* rec, const double* tru, int32_t masked,
+                            double* out3, wf_mem mem) {
+  if (!c || !rec || !tru || !out3) return c ? finish(c, fail(WF_EINVAL, "null argument")) : WF_EINVAL;
+  Status s = need(c->have_grid && (!masked || c->have_mask), "needs the grid (and mask)");
+  if (!s.ok()) return finish(c, s);
+  auto run = [&]() -> Status {
+    WF_TRY(set_device(c));
+    const Grid& g = c->od.g;
+    DevBuf fr, ft, flag;
+    const double *r = rec, *t = tru;
+    if (mem == WF_HOST) {
+      WF_TRY(fr.ensure(c->al, (size_t)g.m * 8));
+      WF_TRY(ft.ensure(c->al, (size_t)g.m * 8));
+      WF_TRY(upload(fr.p, rec, (size_t)g.m * 8, WF_HOST, c->stream));
+      WF_TRY(upload(ft.p, tru, (size_t)g.m * 8, WF_HOST, c->stream));
+      r = fr.as<double>();
+      t = ft.as<double>();
+    }
+    double sm[6];
+    bool kl_ok = true;
+    WF_TRY(compare_sums(r, t, masked ? c->od.w64.as<double>() : nullptr, g.m, c->mpartials, flag,
+                        c->al, sm, &kl_ok, c->stream));
+    const double n = sm[5];
+    out3[0] = (sm[1] > 0 && sm[2] > 0) ? sm[0] / (std::sqrt(sm[1]) * std::sqrt(sm[2])) : NAN;
+    out3[1] = n > 0 ? std::sqrt(sm[3] / n) : NAN;
+    out3[2] = (n > 0 && kl_ok) ? sm[4] / n : NAN;
+    return {};
+  };
+  return finish(c, run());
+}
+
+wf_status wf_inverse_weighting(wf_ctx* c, wf_scheme scheme, int32_t ss, double* out, wf_mem mem) {
+  if (!c || !out) return c ? finish(c, fail(WF_EINVAL, "null output")) : WF_EINVAL;
+  Status s = need(c->have_grid && c->have_mask && c->have_gal,
+                  "needs wf_set_grid, wf_set_mask and wf_set_galaxies");
+  if (!s.ok()) return finish(c, s);
+  if (scheme < WF_NGP || scheme > WF_TSC) return finish(c, fail(WF_EINVAL, "unknown scheme"));
+  if (ss != 1 && ss != 2) return finish(c, fail(WF_EINVAL, "supersample must be 1 or 2"));
+  auto run = [&]() -> Status {
+    WF_TRY(set_device(c));
+    const Grid& g = c->od.g;
+    const int nf = ss * g.n;
+    const int64_t mf = (int64_t)nf * nf * nf;
+    DevBuf fine, field;
+    WF_TRY(fine.ensure(c->al, (size_t)mf * 8));
+    WF_HIP(launch_fill_f64(fine.as<double>(), mf, c->stream));
+    WF_TRY(clear_flag(c));
+    WF_HIP(launch_deposit_iw(scheme, c->xyz.as<double>(), c->n_gal, (double)nf / g.box, nf,
+                             (double)g.n / g.box, g.n, c->od.w64.as<double>(), fine.as<double>(),
+                             c->flag.as<int>(), c->stream));
+    int bad = 0;
+    WF_TRY(read_flag(c, &bad));
+    if (bad) return fail(WF_EINVAL, "a galaxy lies on a node with w = 0");
+    double* dst = out;
+    if (mem == WF_HOST) {
+      WF_TRY(field.ensure(c->al, (size_t)g.m * 8));
+      dst = field.as<double>();
+    }
+    WF_TRY(run_lowpass(c->al, c->od, c->dw, nullptr, fine.as<double>(), 1.0, ss, dst, c->stream));
+    c->dw.fine_spec.release();
+    c->dw.spec_y.release();
+    c->dw.spec_c.release();
+    fine.release();
+    // nbar of eq:nmean
+    const double nbar = c->sumw > 0 ? (double)c->n_gal / c->sumw : 0.0;
+    if (!(nbar > 0.0)) return fail(WF_EINVAL, "no galaxies: nbar = 0");
+    WF_HIP(launch_overdensity(dst, g.m, 1.0 / nbar, c->stream));
+    if (mem == WF_HOST) WF_TRY(download(out, dst, (size_t)g.m * 8, WF_HOST, c->stream));
+    WF_HIP(hipStreamSynchronize(c->stream));
+    return {};
+  };
+  return finish(c, run());
+}
+
 wf_status wf_profile_enable(wf_ctx* c, int32_t on) {
   if (!c) return WF_EINVAL;
   Status s = set_device(c);

@@ -321,6 +321,13 @@ static StrArgs<T> str_args(const OperatorData& od, cplx<T>* spec, bool xpass, co
 }
 
 template <typename T>
+StrArgs<T> spectrum_args(const OperatorData& od, cplx<T>* spec, bool xpass) {
+  return str_args<T>(od, spec, xpass, nullptr, SKIP_NONE);
+}
+template StrArgs<float> spectrum_args<float>(const OperatorData&, cplx<float>*, bool);
+template StrArgs<double> spectrum_args<double>(const OperatorData&, cplx<double>*, bool);
+
+template <typename T>
 Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T* p, T* x,
                        cplx<T>* spec, int zout_mode, T* out, const T* aux, const double* bvec,
                        CgState* st, double* partials, int nrhs, int skip, hipStream_t s) {
@@ -613,8 +620,18 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
     WF_HIP(launch_deposit(scheme, xyz, ngal, c, nf, grid, s));
   }
   const double unit = scheme == WF_NGP ? 1.0 : std::ldexp(1.0, -39);
+  return run_lowpass(al, od, dw, grid, nullptr, unit, ss, nobs, s);
+}
+
+Status run_lowpass(const Allocator& al, const OperatorData& od, DepositWork& dw,
+                   const long long* grid, const double* dgrid, double unit, int ss, double* nobs,
+                   hipStream_t s) {
+  const Grid& g = od.g;
+  const int n = g.n, nf = ss * n;
+  const int64_t mf = (int64_t)nf * nf * nf;
   if (ss == 1) {
-    WF_HIP(launch_i64_to_f64(nobs, grid, unit, g.m, s));
+    if (grid) WF_HIP(launch_i64_to_f64(nobs, grid, unit, g.m, s));
+    else WF_HIP(hipMemcpyAsync(nobs, dgrid, (size_t)g.m * 8, hipMemcpyDeviceToDevice, s));
     return {};
   }
   // fine forward transform, keeping kz < n/2
@@ -633,12 +650,13 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
   const auto* twf = dw.tw_fine.as<double2>();
   ZfwdArgs<double> zf{};
   zf.gin = grid;
+  zf.in = dgrid;
   zf.unit = unit;
   zf.out_main = fs;
   zf.out_nyq = nullptr;
   zf.nkz_out = h;
   zf.tw = twf;
-  WF_HIP(launch_zfwd<double>(nf, ZIN_I64, zf, (int64_t)nf * nf, 1, s));
+  WF_HIP(launch_zfwd<double>(nf, grid ? ZIN_I64 : ZIN_REAL, zf, (int64_t)nf * nf, 1, s));
 
   // y: fine [nf x][nf y][h] -> [nf x][n y][h], keeping |m_y| < n/2
   const int tbf = strided_tb(nf, true);

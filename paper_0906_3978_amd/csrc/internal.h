@@ -178,6 +178,28 @@ struct DepositWork {
   DevBuf grid, fine_spec, spec_y, spec_c, tw_fine, flag;
   int tw_fine_n = 0;  // length tw_fine holds the twiddles of
 };
+// The low-pass and resampling of a deposit grid (int64 units, or FP64 when
+// `grid` is null) into the target-grid n_obs (Sec. 3.1.2).
+Status run_lowpass(const Allocator& al, const OperatorData& od, DepositWork& dw,
+                   const long long* grid, const double* dgrid, double unit, int ss, double* nobs,
+                   hipStream_t s);
+template <typename T> StrArgs<T> spectrum_args(const OperatorData& od, cplx<T>* spec, bool xpass);
+// post-processing (post.hip)
+hipError_t launch_rsd_factor(double dk2, double beta, double sigma, double* out, int64_t len,
+                             hipStream_t s);
+hipError_t launch_filter_table(int kind, double dk2, double a, double b, double c,
+                               const double* table, int64_t len, double scale, double* out,
+                               int* flag, hipStream_t s);
+Status filter_passes(const OperatorData& od, const double* hrows, const double* in,
+                     cplx<double>* spec, double* out, hipStream_t s);
+Status field_sums(const double* v, const double* w, int64_t m, DevBuf& parts, const Allocator& al,
+                  double out[5], hipStream_t s);
+Status compare_sums(const double* rec, const double* tru, const double* w, int64_t m, DevBuf& parts,
+                    DevBuf& flag, const Allocator& al, double out[6], bool* kl_ok, hipStream_t s);
+hipError_t launch_deposit_iw(int scheme, const double* xyz, int64_t ngal, double c, int nd,
+                             double ct, int n, const double* w, double* grid, int* flag,
+                             hipStream_t s);
+hipError_t launch_overdensity(double* v, int64_t m, double inv_nbar, hipStream_t s);
 Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
                    const double* xyz_dev, int64_t ngal, int scheme, int supersample,
                    double* nobs_dev, hipStream_t s);
