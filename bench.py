@@ -199,6 +199,59 @@ def batch_run(nrhs, tol, precond="prior"):
     return res
 
 
+def post_run(ctx, wl, field, reps=3):
+    """The post-solve functions on the 512^3 solution already in HBM: RSD
+    deconvolution (beta = 0.42, sigma = 500 km/s / H0, b = 1), Gaussian
+    smoothing at r_S = 5 Mpc, masked moments, the inverse-weighting field of
+    the same catalogue and the Sec. 4.1 measures between the two smoothed
+    fields.  Each is timed on its own (device pointers, synchronised)."""
+    import torch
+    n = wl.n
+    dec = torch.empty_like(field)
+    sm = torch.empty_like(field)
+    iw = torch.empty_like(field)
+    iws = torch.empty_like(field)
+    m = n ** 3
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t) / reps
+
+    beta, sigma = 0.42, 500.0 / 73.0
+    _, t_rsd = timed(lambda: ctx.rsd_factor(beta, sigma))
+    _, t_dec = timed(lambda: ctx.fourier_filter(field, "rsd_deconv", a=beta, b=sigma, c=1.0,
+                                                out=dec))
+    _, t_sm = timed(lambda: ctx.fourier_filter(dec, "gauss", a=5.0, out=sm))
+    mom, t_mom = timed(lambda: ctx.field_moments(sm, masked=True))
+    _, t_iw = timed(lambda: ctx.inverse_weighting(wl.scheme, wl.supersample, out=iw))
+    ctx.fourier_filter(iw, "gauss", a=5.0, out=iws)
+    cmp_, t_cmp = timed(lambda: ctx.compare_fields(sm, iws, masked=True))
+    # FP64 bytes per cell of the five filter passes: the half spectrum is 8 B
+    # per cell, so z R2C 8 + 8, y 8 + 8, x 8 + 8, y 8 + 8, z C2R 8 + 8; moments
+    # read v and w, compare reads rec, truth and w
+    filt_b, mom_b, cmp_b = 80 * m, 16 * m, 24 * m
+
+    def gbs(b, t):
+        return round(b / t / 1e9, 1)
+    res = {"n": n, "reps": reps,
+           "rsd_factor_ms": round(1e3 * t_rsd, 3),
+           "rsd_deconv_ms": round(1e3 * t_dec, 3), "rsd_deconv_gbs": gbs(filt_b, t_dec),
+           "gauss_ms": round(1e3 * t_sm, 3), "gauss_gbs": gbs(filt_b, t_sm),
+           "moments_ms": round(1e3 * t_mom, 3), "moments_gbs": gbs(mom_b, t_mom),
+           "inverse_weighting_ms": round(1e3 * t_iw, 3),
+           "compare_ms": round(1e3 * t_cmp, 3), "compare_gbs": gbs(cmp_b, t_cmp),
+           "filter_bytes_per_cell": 80,
+           "moments_smoothed_masked": [round(x, 6) for x in mom],
+           "measures_wf_vs_iw_rs5": [round(x, 6) for x in cmp_]}
+    log(f"[post] {res}")
+    return res
+
+
 def traffic_for(kernel, launch_bytes):
     """HBM bytes per launch from committed rocprofv3 PMC counters, if they were
     taken on the current kernel sources."""
@@ -235,6 +288,8 @@ def main():
                     help="profiling run: one deposit, this many mixed iterations (of --precond) "
                          "and a 1 GiB device copy (the reference for scaling HBM counters), "
                          "then exit")
+    ap.add_argument("--no-post", action="store_true",
+                    help="skip timing the post-solve functions (filters, moments, IW)")
     ap.add_argument("--serve", type=int, default=0,
                     help="also run a serving stream of this many requests")
     ap.add_argument("--batch", type=int, default=0,
@@ -374,6 +429,13 @@ def main():
                  "speedup_of_prior_split": round(tp / (info.time_ms * 1e-3), 3)}
         log(f"[bench] plain mixed solve {tp:.3f} s iters={infp.iters_total}")
 
+    post = None
+    if not args.no_post:
+        ctx.set_galaxies(xyz_d)
+        ctx.deposit(wl.scheme, wl.supersample)
+        ctx.solve(out=out, **solve_kw)
+        post = post_run(ctx, wl, out)
+
     cpu = None
     if not args.no_cpu_baseline:
         iters_ref = fp64["iters"] if fp64 else info.iters_total
@@ -414,6 +476,7 @@ def main():
         "kernels": per_kernel,
         "fp64": fp64,
         "plain_cg": plain,
+        "post": post,
         "cpu_baseline": cpu,
         "serving": serving,
         "batch": batch,
