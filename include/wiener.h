@@ -233,6 +233,46 @@ wf_status wf_solve_batch(wf_ctx* ctx, int32_t nrhs, const double* const* xyz,
                          double* const* s_out, wf_mem mem,
                          wf_solve_info* infos);
 
+/* ---- signal-dependent noise (eq:noisecov, Sec. 3.4) -------------------- */
+/* The SD formulation replaces the averaged noise w / nbar of each observed
+ * cell by lambda^o / nbar^2, lambda^o estimating the expected observed count
+ * w lambda.  The system solved is
+ *   (F^-1 Lambda F + diag(nbar w g)) s = g (n^o - nbar w),  g = nbar w / lambda^o
+ * on cells with w > 0 (cells with w = 0 carry no data and no noise term), with
+ * n^o and nbar from the last wf_deposit.  Counts N are galaxies per nearest
+ * target node (the NGP rule on the target grid).  Estimators:
+ *   WF_NOISE_SD_MEAN       lambda^o = N^o + 1 (flat-prior mean, Sec. 3.4.1)
+ *   WF_NOISE_SD_JACKKNIFE  lambda^o = w (N' + 1) / alpha, N' the counts of a
+ *       binomial thinning that keeps each galaxy with probability alpha / w
+ *       of its node (eq:selfunc; the + 1 keeps every observed cell's noise
+ *       above zero).  Sample j of seed S keeps galaxy g when the first word of
+ *       Philox4x32-10 (Salmon et al. 2011) with counter (g mod 2^32, g div
+ *       2^32, j, 0) and key (S mod 2^32, S div 2^32) is below (alpha / w) 2^32
+ *       (compared in double precision). */
+typedef enum { WF_NOISE_SD_MEAN = 1, WF_NOISE_SD_JACKKNIFE = 2 } wf_noise;
+
+/* Thinned counts N' of jackknife samples first .. first + count - 1 of the
+ * context's galaxies: out holds count x n^3 int32 (sample-major, C order per
+ * sample; only nodes with w > 0 count).  alpha in (0, w] at the node of every
+ * galaxy, else WF_EINVAL.  Needs wf_set_grid, wf_set_mask, wf_set_galaxies.
+ * Synchronises. */
+wf_status wf_jackknife_counts(wf_ctx* ctx, double alpha, uint64_t seed, int64_t first,
+                              int32_t count, int32_t* out, wf_mem mem);
+
+/* SD Wiener reconstruction of the galaxies of the last wf_deposit (which must
+ * follow the last wf_set_galaxies / wf_set_mask / wf_set_grid): nsamples
+ * systems (1 for WF_NOISE_SD_MEAN; jackknife samples first .. first +
+ * nsamples - 1), solved with the batched kernels in groups of up to 16 with
+ * `opts`.  mean_out (n^3) receives the mean of the solutions (the paper's
+ * jackknife estimate); samples_out (nsamples x n^3, may be NULL) each of them;
+ * infos (nsamples, may be NULL) their infos.  Both outputs on `mem`.  Returns
+ * the worst status (outputs written for WF_OK, WF_ENOTCONV and
+ * WF_EBREAKDOWN).  alpha and seed are ignored by WF_NOISE_SD_MEAN.
+ * Synchronises. */
+wf_status wf_solve_sd(wf_ctx* ctx, const wf_solve_opts* opts, int32_t kind, double alpha,
+                      uint64_t seed, int64_t first, int32_t nsamples, double* mean_out,
+                      double* samples_out, wf_mem mem, wf_solve_info* infos);
+
 /* ---- after the solve: redshift space, filters, comparators ------------- */
 /* Redshift-distortion factor of Sec. 3.3.3: the angle average
  *   g(k) = <K D>_mu = int_0^1 (1 + beta mu^2)^2 / (1 + k^2 sigma^2 mu^2 / 2) dmu

@@ -118,6 +118,9 @@ SIGNATURES = {
     "wf_field_moments": (C.c_int, [_V, _P, _I32, _P, C.c_int]),
     "wf_compare_fields": (C.c_int, [_V, _P, _P, _I32, _P, C.c_int]),
     "wf_inverse_weighting": (C.c_int, [_V, C.c_int, _I32, _P, C.c_int]),
+    "wf_jackknife_counts": (C.c_int, [_V, _D, C.c_uint64, C.c_int64, _I32, _P, C.c_int]),
+    "wf_solve_sd": (C.c_int, [_V, C.POINTER(SolveOpts), _I32, _D, C.c_uint64, C.c_int64, _I32,
+                              _P, _P, C.c_int, C.POINTER(SolveInfo)]),
     "wf_profile_enable": (C.c_int, [_V, _I32]),
     "wf_profile_read": (C.c_int, [_V, C.POINTER(Profile)]),
     "wf_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, _SZ, _I32, ALLOC_FN, FREE_FN, _V]),
@@ -422,6 +425,39 @@ class Context:
                                       C.byref(o), op, mem, infos)
         self._check(code, ok=allow)
         return outs, [_info(i) for i in infos]
+
+    # ---- signal-dependent noise ------------------------------------------
+    def jackknife_counts(self, alpha, seed, first=0, count=1, out=None):
+        """Thinned counts N' of jackknife samples first .. first + count - 1
+        (count x n^3 int32)."""
+        n = self.n
+        if out is None:
+            out = np.empty((count, n, n, n), dtype=np.int32)
+        p, mem = _ptr(out)
+        self._check(self._L.wf_jackknife_counts(self._h, float(alpha), int(seed), int(first),
+                                                int(count), p, mem))
+        return out
+
+    def solve_sd(self, kind="mean", alpha=0.0, seed=0, first=0, nsamples=1, mean_out=None,
+                 samples_out=None, keep_samples=False, allow=(WF_OK,), **kw):
+        """Signal-dependent noise reconstruction of the last deposit: kind
+        "mean" (one solve) or "jackknife" (nsamples solves); returns the mean
+        of the solutions, the solutions (if asked for) and the infos."""
+        o = opts(**kw)
+        n = self.n
+        kinds = {"mean": 1, "jackknife": 2}
+        if mean_out is None:
+            mean_out = np.empty((n, n, n), dtype=np.float64)
+        p, mem = _ptr(mean_out)
+        if samples_out is None and keep_samples:
+            samples_out = (np.empty((nsamples, n, n, n), dtype=np.float64) if mem == WF_HOST
+                           else mean_out.new_empty((nsamples, n, n, n)))
+        sp = _ptr(samples_out)[0] if samples_out is not None else None
+        infos = (SolveInfo * nsamples)()
+        code = self._L.wf_solve_sd(self._h, C.byref(o), kinds[kind], float(alpha), int(seed),
+                                   int(first), int(nsamples), p, sp, mem, infos)
+        self._check(code, ok=allow)
+        return mean_out, samples_out, [_info(i) for i in infos]
 
 
 def footprint_bytes(n, supersample=2, precision="mixed", nrhs=1):

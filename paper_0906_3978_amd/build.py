@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwiener.so")
 
 SOURCES = ["fftpass.hip", "kernels.hip", "core.hip", "solver.hip", "api.hip", "server.hip",
-           "post.hip"]
+           "post.hip", "sd.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("WF_OFFLOAD_ARCH", "gfx950")

@@ -18,6 +18,7 @@ struct wf_ctx {
   OperatorData od;
   bool have_grid = false, have_mask = false, have_power = false, have_gal = false;
   bool have_rhs = false;
+  bool dep_current = false;  // n^o and nbar belong to the current galaxies and mask
   DevBuf xyz, nobs, scal, flag, mpartials;
   int64_t n_gal = 0;
   double sumw = 0.0, nbar = 0.0;
@@ -132,6 +133,7 @@ wf_status wf_set_grid(wf_ctx* c, int32_t n, double box) {
   if (s.ok()) {
     c->od.g.set(n, box);
     c->have_grid = c->have_mask = c->have_power = c->have_gal = c->have_rhs = false;
+    c->dep_current = false;
     c->od.fac_ready = false;
     c->solve_active = false;
     c->dep_scheme = -1;
@@ -175,6 +177,7 @@ wf_status wf_set_mask(wf_ctx* c, const double* w, wf_mem mem) {
   };
   s = run();
   c->have_mask = s.ok();
+  c->dep_current = false;
   c->have_rhs = false;
   return finish(c, s);
 }
@@ -233,6 +236,7 @@ wf_status wf_set_galaxies(wf_ctx* c, const double* xyz, int64_t n_gal, wf_mem me
   };
   s = run();
   c->have_gal = s.ok();
+  c->dep_current = false;
   return finish(c, s);
 }
 
@@ -269,6 +273,7 @@ wf_status wf_deposit(wf_ctx* c, wf_scheme scheme, int32_t ss) {
   };
   s = run();
   c->have_rhs = s.ok();
+  c->dep_current = s.ok();
   c->solve_active = false;
   return finish(c, s);
 }
@@ -308,6 +313,7 @@ wf_status wf_set_rhs(wf_ctx* c, const double* b, double nbar, wf_mem mem) {
   };
   s = run();
   c->have_rhs = s.ok();
+  c->dep_current = false;
   c->solve_active = false;
   return finish(c, s);
 }
@@ -529,6 +535,86 @@ wf_status wf_solve_batch(wf_ctx* c, int32_t nrhs, const double* const* xyz, cons
   if (infos)
     for (int i = 0; i < nrhs; ++i) infos[i] = inf[i];
   c->have_rhs = false;
+  c->solve_active = false;
+  return finish(c, s);
+}
+
+// ---- signal-dependent noise ----------------------------------------------------
+
+wf_status wf_jackknife_counts(wf_ctx* c, double alpha, uint64_t seed, int64_t first,
+                              int32_t count, int32_t* out, wf_mem mem) {
+  if (!c || !out) return c ? finish(c, fail(WF_EINVAL, "null output")) : WF_EINVAL;
+  Status s = need(c->have_grid && c->have_mask && c->have_gal,
+                  "needs wf_set_grid, wf_set_mask and wf_set_galaxies");
+  if (!s.ok()) return finish(c, s);
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return finish(c, fail(WF_EINVAL, "alpha must be > 0"));
+  if (count <= 0 || first < 0) return finish(c, fail(WF_EINVAL, "need count > 0 and first >= 0"));
+  auto run = [&]() -> Status {
+    WF_TRY(set_device(c));
+    const Grid& g = c->od.g;
+    DevBuf tmp;
+    int32_t* dst = reinterpret_cast<int32_t*>(out);
+    if (mem == WF_HOST) {
+      WF_TRY(tmp.ensure(c->al, (size_t)count * g.m * 4));
+      dst = tmp.as<int32_t>();
+    }
+    WF_HIP(hipMemsetAsync(dst, 0, (size_t)count * g.m * 4, c->stream));
+    WF_TRY(clear_flag(c));
+    WF_HIP(launch_sd_counts(true, c->xyz.as<double>(), c->n_gal, (double)g.n / g.box, g.n,
+                            c->od.w64.as<double>(), alpha, seed, first, count, dst,
+                            c->flag.as<int>(), c->stream));
+    int bad = 0;
+    WF_TRY(read_flag(c, &bad));
+    if (bad) return fail(WF_EINVAL, "alpha exceeds w at the node of a galaxy");
+    if (mem == WF_HOST) WF_TRY(download(out, dst, (size_t)count * g.m * 4, WF_HOST, c->stream));
+    WF_HIP(hipStreamSynchronize(c->stream));
+    return {};
+  };
+  return finish(c, run());
+}
+
+wf_status wf_solve_sd(wf_ctx* c, const wf_solve_opts* opts, int32_t kind, double alpha,
+                      uint64_t seed, int64_t first, int32_t nsamples, double* mean_out,
+                      double* samples_out, wf_mem mem, wf_solve_info* infos) {
+  if (!c || !opts || !mean_out) return c ? finish(c, fail(WF_EINVAL, "null argument")) : WF_EINVAL;
+  Status s = need(c->have_grid && c->have_mask && c->have_power && c->have_gal && c->dep_current,
+                  "wf_solve_sd needs grid, mask, power, galaxies and a wf_deposit of them");
+  if (!s.ok()) return finish(c, s);
+  s = validate_opts(*opts);
+  if (!s.ok()) return finish(c, s);
+  if (kind == WF_NOISE_SD_MEAN) {
+    if (nsamples != 1) return finish(c, fail(WF_EINVAL, "the mean estimator has one sample"));
+  } else if (kind == WF_NOISE_SD_JACKKNIFE) {
+    if (nsamples <= 0 || first < 0) return finish(c, fail(WF_EINVAL, "need nsamples > 0, first >= 0"));
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return finish(c, fail(WF_EINVAL, "alpha must be > 0"));
+  } else {
+    return finish(c, fail(WF_EINVAL, "unknown noise kind"));
+  }
+  s = set_device(c);
+  if (s.ok() && opts->precond == WF_PRECOND_PRIOR) s = ensure_split_fac(c->al, c->od, c->stream);
+  if (!s.ok()) return finish(c, s);
+  SdRequest rq;
+  rq.od = &c->od;
+  rq.al = &c->al;
+  rq.xyz = c->xyz.as<double>();
+  rq.n_gal = c->n_gal;
+  rq.nobs = c->nobs.as<double>();
+  rq.nbar = c->nbar;
+  rq.kind = kind;
+  rq.alpha = alpha;
+  rq.seed = seed;
+  rq.first = first;
+  rq.nsamples = nsamples;
+  rq.opts = *opts;
+  rq.mean_out = mean_out;
+  rq.samples_out = samples_out;
+  rq.mem = mem;
+  rq.flag = c->flag.as<int>();
+  rq.stream = c->stream;
+  std::vector<wf_solve_info> inf(nsamples);
+  s = run_sd(rq, inf.data());
+  if (infos)
+    for (int i = 0; i < nsamples; ++i) infos[i] = inf[i];
   c->solve_active = false;
   return finish(c, s);
 }

@@ -301,6 +301,20 @@ template <typename T> static const T* w_of(const OperatorData& od) {
   if constexpr (sizeof(T) == 8) return od.w64.as<T>();
   else return od.w32.as<T>();
 }
+// the noise diagonal of the operator: nbar w (the mask, shared by all RHS, times
+// each RHS's nbar) or the per-RHS signal-dependent arrays nbar w g
+template <typename T, typename Args> static void set_noise_diag(const OperatorData& od, Args& a) {
+  if (od.sd) {
+    if constexpr (sizeof(T) == 8) a.w = od.dg64.as<T>();
+    else a.w = od.dg32.as<T>();
+    a.rhs_w = od.g.m;
+    a.w_scaled = 1;
+  } else {
+    a.w = w_of<T>(od);
+    a.rhs_w = 0;
+    a.w_scaled = 0;
+  }
+}
 
 template <typename T>
 static StrArgs<T> str_args(const OperatorData& od, cplx<T>* spec, bool xpass, const CgState* st,
@@ -375,7 +389,7 @@ Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T
   zi.rhs_out = g.m;
   zi.aux = aux;
   zi.rhs_aux = g.m;
-  zi.w = w_of<T>(od);
+  set_noise_diag<T>(od, zi);
   zi.bvec = bvec;
   zi.rhs_b = g.m;
   zi.scale = 1.0;
@@ -384,8 +398,9 @@ Status operator_passes(const OperatorData& od, int zin_mode, const T* in_or_r, T
   zi.st = st;
   zi.skip = skip;
   {
-    // spectrum in; aux and w in (w once for all RHS); result out; RES also reads b
-    const double wb = (double)sizeof(T) * g.m;
+    // spectrum in; aux and the noise diagonal in (the mask once for all RHS, SD
+    // arrays per RHS); result out; RES also reads b
+    const double wb = (double)sizeof(T) * g.m * (od.sd ? nrhs : 1);
     double zb = sb + 2 * vb + wb;
     if (zout_mode == ZOUT_RES) zb += 8.0 * g.m * nrhs;
     {
@@ -497,13 +512,13 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
     zm.spec_nyq = work + g.spec_main;
     zm.rhs_main = g.spec_total;
     zm.rhs_nyq = g.spec_total;
-    zm.w = w_of<T>(od);
+    set_noise_diag<T>(od, zm);
     zm.tw = tw_of<T>(od);
     zm.st = st;
     zm.skip = skip;
-    // spectrum in and out, w in (once for all RHS)
+    // spectrum in and out, the noise diagonal in (once for all RHS unless SD)
     ProfScope ps(od.prof, f64 ? WF_PROF_SZW_F64 : WF_PROF_SZW_F32,
-                 sb + (double)sizeof(T) * g.m, s);
+                 sb + (double)sizeof(T) * g.m * (od.sd ? nrhs : 1), s);
     WF_HIP(launch_zmid<T>(g.n, zm, g.nrows, nrhs, s));
   }
   {

@@ -253,7 +253,8 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
   double acc = 0.0;
   T* out = a.out + rhs * a.rhs_out;
   T nbar = T(0);
-  if constexpr (MODE != ZOUT_REAL) nbar = (T)st->nbar;
+  if constexpr (MODE != ZOUT_REAL) nbar = a.w_scaled ? T(1) : (T)st->nbar;
+  const T* wr = a.w + rhs * a.rhs_w;
 #pragma unroll
   for (int c = 0; c < PER3; ++c) {
     const int q = threadIdx.x + c * NT;
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
     } else if constexpr (MODE == ZOUT_CGQ || MODE == ZOUT_APPLY) {
       const T* p = a.aux + rhs * a.rhs_aux;
       const R p0 = ld16(p + i0), p1 = ld16(p + i1);
-      const R w0 = ld16(a.w + i0), w1 = ld16(a.w + i1);
+      const R w0 = ld16(wr + i0), w1 = ld16(wr + i1);
       const R q0 = re + (nbar * w0) * p0;
       const R q1 = imv + (nbar * w1) * p1;
       st16(out + i0, q0);
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
       const T* x = a.aux + rhs * a.rhs_aux;
       const double* bb = a.bvec + rhs * a.rhs_b;
       const R x0 = ld16(x + i0), x1 = ld16(x + i1);
-      const R w0 = ld16(a.w + i0), w1 = ld16(a.w + i1);
+      const R w0 = ld16(wr + i0), w1 = ld16(wr + i1);
       const R r0 = ld16(bb + i0) - (re + (nbar * w0) * x0);
       const R r1 = ld16(bb + i1) - (imv + (nbar * w1) * x1);
       st16(out + i0, r0);
@@ -305,7 +306,8 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
 
 // ---------------------------------------------------------------------------
 // z middle pass of the prior-split operator: half spectrum -> real rows ->
-// times nbar w -> half spectrum, in place (the rows of a block are its own)
+// times the noise diagonal -> half spectrum, in place (the rows of a block are
+// its own)
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__(NT) void k_zmid(ZmidArgs<T> a) {
@@ -366,7 +368,8 @@ __global__ __launch_bounds__(NT) void k_zmid(ZmidArgs<T> a) {
   fft_tile<T, N, NB, NT, false, +1>(lds, twl);
 
   // real rows (re: r0, im: r0 + 1) times nbar w
-  const T nbar = (T)st->nbar;
+  const T nbar = a.w_scaled ? T(1) : (T)st->nbar;
+  const T* wr = a.w + rhs * a.rhs_w;
   constexpr int ITEMS3 = NB * N / RW;
   constexpr int PER3 = (ITEMS3 + NT - 1) / NT;
 #pragma unroll
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(NT) void k_zmid(ZmidArgs<T> a) {
     if (ITEMS3 % NT == 0 || q < ITEMS3) {
       const int b = q / (N / RW), z = (q - b * (N / RW)) * RW;
       const int64_t i0 = (row0 + 2 * b) * N + z;
-      const R w0 = nbar * ld16(a.w + i0), w1 = nbar * ld16(a.w + i0 + N);
+      const R w0 = nbar * ld16(wr + i0), w1 = nbar * ld16(wr + i0 + N);
 #pragma unroll
       for (int j = 0; j < RW; ++j) {
         const V v = lds[b * N + z + j];

@@ -113,6 +113,10 @@ struct OperatorData {
   DevBuf xlam64, xlam32;  // the same, expanded into the x-pass rows
   DevBuf fac64, fac32;    // prior-split factor c over (|my|, |mx|, kz), built on demand
   bool fac_ready = false;
+  // signal-dependent noise: while sd is set the operator's noise diagonal is
+  // dg (nbar w g per RHS, n^3 apart) instead of nbar w
+  bool sd = false;
+  DevBuf dg64, dg32;
   Profiler* prof = nullptr;   // optional
 };
 

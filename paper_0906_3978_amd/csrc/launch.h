@@ -35,7 +35,9 @@ template <typename T> struct ZinvArgs {
   int64_t rhs_out;
   const T* aux;             // CGQ: p; RES: x; APPLY: v
   int64_t rhs_aux;
-  const T* w;               // mask (shared by all RHS)
+  const T* w;               // noise diagonal: the mask (times the RHS's nbar) or,
+  int64_t rhs_w;            // with w_scaled, per-RHS arrays nbar w g (stride rhs_w)
+  int32_t w_scaled;
   const double* bvec;       // RES: b
   int64_t rhs_b;
   double scale;             // REAL: output scale
@@ -51,7 +53,9 @@ template <typename T> struct ZmidArgs {
   cplx<T>* spec_main;       // [row][N/2]
   cplx<T>* spec_nyq;        // [row]
   int64_t rhs_main, rhs_nyq;
-  const T* w;               // mask (shared by all RHS)
+  const T* w;               // as in ZinvArgs
+  int64_t rhs_w;
+  int32_t w_scaled;
   const cplx<T>* tw;
   const CgState* st;        // required
   int32_t skip;             // SKIP_*

@@ -60,4 +60,32 @@ Status run_batch(const OperatorData& od, const Allocator& al, DepositWork& dw,
 
 size_t footprint_bytes(int n, int ss, wf_precision prec, int nrhs, bool split);
 
+int severity(wf_status s);
+
+// signal-dependent noise solves (sd.hip)
+constexpr int SD_CHUNK = 16;   // RHS per batched solve
+struct SdRequest {
+  OperatorData* od = nullptr;
+  const Allocator* al = nullptr;
+  const double* xyz = nullptr;  // device, n_gal x 3
+  int64_t n_gal = 0;
+  const double* nobs = nullptr;  // device, n^3
+  double nbar = 0.0;
+  int kind = WF_NOISE_SD_MEAN;
+  double alpha = 0.0;
+  uint64_t seed = 0;
+  int64_t first = 0;
+  int nsamples = 1;
+  wf_solve_opts opts{};
+  double* mean_out = nullptr;
+  double* samples_out = nullptr;
+  wf_mem mem = WF_HOST;
+  int* flag = nullptr;  // device int
+  hipStream_t stream = nullptr;
+};
+Status run_sd(const SdRequest& rq, wf_solve_info* infos);
+hipError_t launch_sd_counts(bool thin, const double* xyz, int64_t ngal, double ct, int n,
+                            const double* w, double alpha, uint64_t seed, int64_t first, int K,
+                            int32_t* counts, int* flag, hipStream_t s);
+
 }  // namespace wf

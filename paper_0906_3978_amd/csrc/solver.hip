@@ -32,6 +32,15 @@ Status validate_opts(const wf_solve_opts& o) {
   return {};
 }
 
+int severity(wf_status s) {
+  switch (s) {
+    case WF_OK: return 0;
+    case WF_ENOTCONV: return 1;
+    case WF_EBREAKDOWN: return 2;
+    default: return 3;
+  }
+}
+
 namespace {
 
 template <typename T> struct Vecs {
@@ -129,14 +138,6 @@ wf_status map_cg_status(int32_t st) {
   }
 }
 
-int severity(wf_status s) {
-  switch (s) {
-    case WF_OK: return 0;
-    case WF_ENOTCONV: return 1;
-    case WF_EBREAKDOWN: return 2;
-    default: return 3;
-  }
-}
 
 struct Timer {
   hipEvent_t a = nullptr, b = nullptr;

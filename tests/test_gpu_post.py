@@ -95,3 +95,26 @@ def test_inverse_weighting(ctx, scheme, ss):
     got = ctx.inverse_weighting(scheme, ss)
     want = op.inverse_weighting(xyz, n, box, w, scheme, ss)
     assert rel_max(got + 1.0, want + 1.0) < 1e-12
+
+
+def test_redshift_space_prior_and_deconvolution(ctx):
+    """Sec. 3.3.3: the prior in redshift space is <KD>_mu P; the solve with it,
+    then eq:DEC with a constant bias, against the oracle's."""
+    from oracle import wiener as ow
+    wl = synth.Workload("rsd32", 32, 300.0, "cic", 2, 20000, 515, "bbks")
+    ptab = wl.ptab()
+    w = wl.mask()
+    xyz = wl.catalogue(ptab, w).xyz
+    ctx.set_grid(wl.n, wl.box)
+    ctx.set_mask(w)
+    ps = ptab * ctx.rsd_factor(BETA, SIGMA)
+    ctx.set_power(ps)
+    ctx.set_galaxies(xyz)
+    ctx.deposit("cic", 2)
+    x, info = ctx.solve(precision="fp64", precond="prior", tol=1e-12, max_iter=20000)
+    ps_ref = ptab * op.rsd_factor_table(wl.n, wl.box, BETA, SIGMA)
+    ref = ow.reconstruct(xyz, wl.n, wl.box, w, ps_ref, "cic", 2, 1e-12, 20000)
+    assert rel_max(x, ref["x"]) < 1e-9
+    dec = ctx.fourier_filter(x, "rsd_deconv", a=BETA, b=SIGMA, c=1.3)
+    want = op.fourier_filter(ref["x"], op.deconv_table(wl.n, wl.box, BETA, SIGMA, 1.3))
+    assert rel_max(dec, want) < 1e-9
