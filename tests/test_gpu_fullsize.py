@@ -1,0 +1,66 @@
+"""The 512^3 workload at full size against the oracle's reference solution
+(plain FP64 CG to a relative residual of 1e-12, written by
+tests/golden/make_reference.py and stored as every 16th cell along each axis,
+float32): the error of the solves the benchmark times, on sampled outputs."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+from gpu_util import context
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+STRIDE = 16
+
+
+@pytest.fixture(scope="module")
+def full():
+    wl = synth.workload("bbks512")
+    with open(os.path.join(GOLDEN, "bbks512_n512_meta.json")) as fh:
+        meta = json.load(fh)
+    ref = np.load(os.path.join(GOLDEN, f"bbks512_n512_x_s{STRIDE}.npy")).astype(np.float64)
+    ptab = wl.ptab()
+    w = wl.mask()
+    cat = wl.catalogue(ptab, w)
+    assert len(cat.xyz) == meta["n_gal"]
+    ctx = context()
+    ctx.set_grid(wl.n, wl.box)
+    ctx.set_mask(w)
+    ctx.set_power(ptab)
+    ctx.set_galaxies(cat.xyz)
+    ctx.deposit(wl.scheme, wl.supersample)
+    yield dict(ctx=ctx, ref=ref, meta=meta)
+    ctx.close()
+
+
+def _err(x, full):
+    s = x[::STRIDE, ::STRIDE, ::STRIDE]
+    ref = full["ref"]
+    return float(np.linalg.norm(s - ref) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("precond,tol", [("prior", 3e-7), ("none", 2e-9)])
+def test_mixed_solve_error_at_512(full, precond, tol):
+    """The benchmark's solves (mixed precision, refinement tolerance per
+    preconditioning) reach a relative L2 error below 1e-6."""
+    x, info = full["ctx"].solve(precision="mixed", precond=precond, tol=tol, max_iter=100000)
+    err = _err(x, full)
+    norm_err = abs(np.linalg.norm(x) / full["meta"]["x_norm"] - 1.0)
+    print(f"512^3 mixed {precond} tol {tol:g}: iters {info.iters_total} sampled rel L2 error "
+          f"{err:.3e}, |x| off by {norm_err:.2e}")
+    assert info.status == 0
+    assert err < 1e-6
+    assert norm_err < 1e-6
+
+
+def test_fp64_solve_error_at_512(full):
+    x, info = full["ctx"].solve(precision="fp64", precond="prior", tol=1e-10, max_iter=100000)
+    err = _err(x, full)
+    print(f"512^3 fp64 prior tol 1e-10: iters {info.iters_total} sampled rel L2 error {err:.3e}")
+    # the reference is stored in float32 (relative rounding 6e-8 per value)
+    assert err < 2e-7
