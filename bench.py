@@ -252,6 +252,58 @@ def post_run(ctx, wl, field, reps=3):
     return res
 
 
+def sd_run(nsamples, precond="prior", tol=1e-6):
+    """Signal-dependent noise jackknife (Sec. 3.4): nsamples SD Wiener solves
+    of one catalogue at the paper's mock-test size (128^3 / 500 Mpc, 2x
+    supersampled CIC, BBKS prior, 60 deg cap), each with its own thinned
+    noise estimate (alpha = 0.9 min w), mixed precision, solved 16 to a batch;
+    the mean of the solutions is the estimate.  Also the flat-prior mean
+    estimator (one solve) and the LSQ solve of the same data for reference."""
+    import synth
+    import torch
+    import paper_0906_3978_amd as wf
+    wl = synth.Workload("sd128", 128, 500.0, "cic", 2, 400_000, 7001, "bbks")
+    ptab = wl.ptab()
+    w = wl.mask()
+    cat = wl.catalogue(ptab, w)
+    dev = torch.device("cuda:0")
+    ctx = wf.Context(0)
+    ctx.set_grid(wl.n, wl.box)
+    ctx.set_mask(torch.from_numpy(w).to(dev))
+    ctx.set_power(torch.from_numpy(ptab).to(dev))
+    ctx.set_galaxies(torch.from_numpy(cat.xyz).to(dev))
+    ctx.deposit(wl.scheme, wl.supersample)
+    mean = torch.empty((wl.n,) * 3, dtype=torch.float64, device=dev)
+    alpha = 0.9 * float(w[w > 0].min())
+    kw = dict(precision="mixed", precond=precond, tol=tol, max_iter=100000)
+    ctx.solve_sd("jackknife", alpha=alpha, seed=11, nsamples=16, mean_out=mean, **kw)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, _, infos = ctx.solve_sd("jackknife", alpha=alpha, seed=11, nsamples=nsamples,
+                               mean_out=mean, **kw)
+    torch.cuda.synchronize()
+    t_jk = time.perf_counter() - t
+    t = time.perf_counter()
+    _, _, minf = ctx.solve_sd("mean", mean_out=mean, **kw)
+    torch.cuda.synchronize()
+    t_mean = time.perf_counter() - t
+    t = time.perf_counter()
+    _, linf = ctx.solve(out=mean, **kw)
+    torch.cuda.synchronize()
+    t_lsq = time.perf_counter() - t
+    iters = [i.iters_total for i in infos]
+    res = {"n": wl.n, "n_gal": int(len(cat.xyz)), "nsamples": nsamples, "alpha": round(alpha, 4),
+           "precond": precond, "tol": tol, "jackknife_s": round(t_jk, 3),
+           "sd_solves_per_s": round(nsamples / t_jk, 2),
+           "iters_min_max": [min(iters), max(iters)],
+           "worst_rel_res_true": max(i.rel_res_true for i in infos),
+           "sd_mean_estimator_s": round(t_mean, 4), "sd_mean_iters": minf[0].iters_total,
+           "lsq_s": round(t_lsq, 4), "lsq_iters": linf.iters_total}
+    log(f"[sd] {res}")
+    ctx.close()
+    return res
+
+
 def traffic_for(kernel, launch_bytes):
     """HBM bytes per launch from committed rocprofv3 PMC counters, if they were
     taken on the current kernel sources."""
@@ -290,6 +342,8 @@ def main():
                          "then exit")
     ap.add_argument("--no-post", action="store_true",
                     help="skip timing the post-solve functions (filters, moments, IW)")
+    ap.add_argument("--sd", type=int, default=0,
+                    help="also run this many signal-dependent-noise jackknife solves at 128^3")
     ap.add_argument("--serve", type=int, default=0,
                     help="also run a serving stream of this many requests")
     ap.add_argument("--batch", type=int, default=0,
@@ -445,6 +499,7 @@ def main():
 
     serving = serve(args.serve, args.tol, args.precond) if args.serve else None
     batch = batch_run(args.batch, args.tol, args.precond) if args.batch else None
+    sdres = sd_run(args.sd, args.precond) if args.sd else None
 
     lat_ms = sorted(1e3 * x for x in lat)
     res = {
@@ -480,6 +535,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "batch": batch,
+        "signal_dependent": sdres,
     }
     print(json.dumps(res))
 

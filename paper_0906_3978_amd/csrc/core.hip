@@ -516,9 +516,10 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
     zm.tw = tw_of<T>(od);
     zm.st = st;
     zm.skip = skip;
-    // spectrum in and out, the noise diagonal in (once for all RHS unless SD)
+    // spectrum in and out (in place), the noise diagonal in (once for all RHS
+    // unless SD)
     ProfScope ps(od.prof, f64 ? WF_PROF_SZW_F64 : WF_PROF_SZW_F32,
-                 sb + (double)sizeof(T) * g.m * (od.sd ? nrhs : 1), s);
+                 2 * sb + (double)sizeof(T) * g.m * (od.sd ? nrhs : 1), s);
     WF_HIP(launch_zmid<T>(g.n, zm, g.nrows, nrhs, s));
   }
   {
@@ -734,10 +735,13 @@ Status run_lowpass(const Allocator& al, const OperatorData& od, DepositWork& dw,
   return {};
 }
 
-double model_bytes_iteration(bool fp64, bool split) {
-  if (split) return fp64 ? 176.0 : 88.0;
-  return fp64 ? 152.0 : 76.0;
-}
-double model_bytes_residual(bool split) { return split ? 120.0 : 104.0; }
+// Bytes per cell of one CG iteration, FP32 (FP64 doubles it).  Both forms
+// come to 76: in the split form a half spectrum is 4 B per cell and the passes
+// move x inverse with the direction update 24 (r, p, x in; p, x, work out),
+// y 8, z middle 12, y 8, x forward with q 12, r update 12.
+double model_bytes_iteration(bool fp64, bool /*split*/) { return fp64 ? 152.0 : 76.0; }
+// FP64 residual b - A x, also 104 in both forms (split: x inverse 16, y 16,
+// z middle 24, y 16, x forward with y and b in 32)
+double model_bytes_residual(bool /*split*/) { return 104.0; }
 
 }  // namespace wf
