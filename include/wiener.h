@@ -247,7 +247,7 @@ wf_status wf_solve_batch(wf_ctx* ctx, int32_t nrhs, const double* const* xyz,
  *       of its node (eq:selfunc; the + 1 keeps every observed cell's noise
  *       above zero).  Sample j of seed S keeps galaxy g when the first word of
  *       Philox4x32-10 (Salmon et al. 2011) with counter (g mod 2^32, g div
- *       2^32, j, 0) and key (S mod 2^32, S div 2^32) is below (alpha / w) 2^32
+ *       2^32, j mod 2^32, 0) and key (S mod 2^32, S div 2^32) is below (alpha / w) 2^32
  *       (compared in double precision). */
 typedef enum { WF_NOISE_SD_MEAN = 1, WF_NOISE_SD_JACKKNIFE = 2 } wf_noise;
 
