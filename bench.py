@@ -121,7 +121,7 @@ def serve(n_req, tol, precond="prior", seed=5000):
         t0 = time.perf_counter()
         for r in reqs:
             x, info = srv.wait(submit(srv, r), r[0].n, timeout=600)
-            alone.append((x, info))
+            alone.append((hashlib.sha256(x.tobytes()).hexdigest(), info))
         t_alone = time.perf_counter() - t0
     cap = n_req / t_alone
     rate = 0.7 * cap
@@ -136,9 +136,12 @@ def serve(n_req, tol, precond="prior", seed=5000):
             while time.perf_counter() - t0 < next_t:
                 time.sleep(0.0002)
             tickets.append(submit(srv, r))
-        outs = [srv.wait(tk, r[0].n, timeout=600) for tk, r in zip(tickets, reqs)]
+        outs = []
+        for tk, r in zip(tickets, reqs):
+            x, info = srv.wait(tk, r[0].n, timeout=600)
+            outs.append((hashlib.sha256(x.tobytes()).hexdigest(), info))
         st = srv.stats()
-    same = all(np.array_equal(a[0], b[0]) for a, b in zip(alone, outs))
+    same = all(a[0] == b[0] for a, b in zip(alone, outs))
     worst = max(b[1].rel_res_true for b in outs)
     res = {"requests": n_req, "grids": sorted(set(r[0].n for r in reqs)),
            "isolated_solves_per_s": round(cap, 4), "arrival_rate_per_s": round(rate, 4),
@@ -321,7 +324,7 @@ def traffic_for(kernel, launch_bytes):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="bbks512")
     ap.add_argument("--n", type=int, default=None, help="override the grid size (testing)")
@@ -420,6 +423,16 @@ def main():
     info = infos[-1]
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s: {value:.4f} solves/s; "
         f"iters={info.iters_total} outer={info.outer_steps} rel_res_true={info.rel_res_true:.2e}")
+
+    # error of the last step's solution against the oracle's reference solution
+    # of this workload (FP64 CG to 1e-12), stored as every 16th cell per axis
+    err_ref = None
+    ref_path = os.path.join(ROOT, "tests", "golden", f"{wl.name}_n{n}_x_s16.npy")
+    if os.path.exists(ref_path):
+        ref = np.load(ref_path).astype(np.float64)
+        got = out[::16, ::16, ::16].cpu().numpy()
+        err_ref = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        log(f"[bench] sampled rel. L2 error against the oracle reference: {err_ref:.3e}")
 
     roofline = None
     per_kernel = {}
@@ -524,7 +537,10 @@ def main():
                    "n": n, "box_mpc": wl.box, "n_gal": int(len(cat.xyz)),
                    "scheme": wl.scheme, "supersample": wl.supersample,
                    "precond": args.precond, "tol_outer": args.tol, "iters": info.iters_total,
-                   "outer_steps": info.outer_steps, "rel_res_true": info.rel_res_true},
+                   "outer_steps": info.outer_steps, "rel_res_true": info.rel_res_true,
+                   "rel_l2_error_vs_oracle_reference": err_ref,
+                   "error_reference": "oracle FP64 CG to 1e-12, every 16th cell per axis "
+                                      "(tests/golden)" if err_ref is not None else None},
         "latency_ms": {"p50": round(lat_ms[len(lat_ms) // 2], 3),
                        "p99": round(lat_ms[min(len(lat_ms) - 1, math.ceil(0.99 * len(lat_ms)) - 1)], 3)},
         "roofline": roofline,
