@@ -7,8 +7,11 @@ of the Wiener system (FP32 operator and FFTs, FP64 dots, FP64 residual
 recomputation and iterative refinement) to the refinement tolerance.
 
 Prints one JSON line: solves/s, the roofline figure of the dominant kernel
-(HIP events around its launches during the timed steps), the FP64-CG
-comparison and the oracle timed on the host cores.
+(HIP events around its launches during the timed steps), the error against
+the oracle's stored reference solution, the FP64 and plain-CG comparisons, the
+oracle timed on the host cores, the post-solve functions, and (each can be
+switched off with 0) a 16-RHS batch at 256^3, a serving stream and 200
+signal-dependent-noise jackknife solves at 128^3.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -374,12 +377,14 @@ def main():
                          "then exit")
     ap.add_argument("--no-post", action="store_true",
                     help="skip timing the post-solve functions (filters, moments, IW)")
-    ap.add_argument("--sd", type=int, default=0,
-                    help="also run this many signal-dependent-noise jackknife solves at 128^3")
-    ap.add_argument("--serve", type=int, default=0,
-                    help="also run a serving stream of this many requests")
-    ap.add_argument("--batch", type=int, default=0,
-                    help="also run the multi-RHS batch: this many 256^3 catalogues in one solve")
+    ap.add_argument("--sd", type=int, default=200,
+                    help="also run this many signal-dependent-noise jackknife solves at 128^3 "
+                         "(0: skip)")
+    ap.add_argument("--serve", type=int, default=24,
+                    help="also run a serving stream of this many requests (0: skip)")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="also run the multi-RHS batch: this many 256^3 catalogues in one solve "
+                         "(0: skip)")
     args = ap.parse_args()
     if args.tol is None:
         args.tol = TOLERANCES[args.precond]
