@@ -3,8 +3,9 @@
 One step = the whole hot path on one synthetic catalogue with every input
 already in HBM: copy in the galaxies, fixed-point TSC deposit on the 1024^3
 grid, ideal low-pass to 512^3, data vector, and the mixed-precision CG solve
-of the Wiener system (FP32 operator and FFTs, FP64 dots, FP64 residual
-recomputation and iterative refinement) to the refinement tolerance.
+of the Wiener system (by default on the prior-split system; FP32 operator and
+FFTs, FP64 dots, FP64 residual recomputation with reliable updates) to the
+refinement tolerance.
 
 Prints one JSON line: solves/s, the roofline figure of the dominant kernel
 (HIP events around its launches during the timed steps), the error against
