@@ -176,3 +176,21 @@ def test_sd_jackknife_mixed(ctx, sd32, tol):
         one, _, _ = ctx.solve_sd("jackknife", alpha=d["alpha"], seed=SEED, first=j, nsamples=1,
                                  precision="mixed", precond="prior", tol=tol, max_iter=20000)
         assert np.array_equal(one, xs[j])
+
+
+def test_sd_without_galaxies_is_zero(ctx, sd32):
+    """No galaxies: nbar = 0, so the noise diagonals and the data vanish and
+    every sample's solution is zero (no iteration needed)."""
+    d = sd32
+    wl = d["wl"]
+    ctx.set_grid(wl.n, wl.box)
+    ctx.set_mask(d["w"])
+    ctx.set_power(d["ptab"])
+    ctx.set_galaxies(np.zeros((0, 3)))
+    ctx.deposit("cic", 2)
+    for kind, ns in (("mean", 1), ("jackknife", 3)):
+        mean, xs, infos = ctx.solve_sd(kind, alpha=d["alpha"], seed=1, nsamples=ns,
+                                       keep_samples=True, precision="mixed", precond="prior",
+                                       tol=1e-8, max_iter=100)
+        assert not mean.any() and not xs.any()
+        assert all(i.status == WF_OK and i.iters_total == 0 for i in infos)
