@@ -191,3 +191,27 @@ def test_split_option_checks(ctx, bbks48):
     assert L.wf_solve(ctx._h, ctypes.byref(o), out.ctypes.data, 0, None) == WF_EINVAL
     with pytest.raises(wf.WienerError):
         ctx.solve_begin(precision="fp64", precond="prior", tol=1e-8)
+
+
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 64, 96])
+def test_split_across_grid_sizes(ctx, n):
+    """Converged prior-split solves (FP64 and mixed) on grids whose FFT plans
+    differ (radix 2, 3, 4, 8 mixes; tiles narrower than the default), against
+    the oracle's split CG."""
+    wl = synth.Workload(f"g{n}", n, 4.0 * n, "cic", 2, 40 * n ** 2, 700 + n, "bbks")
+    ptab = wl.ptab()
+    w = wl.mask()
+    xyz = wl.catalogue(ptab, w).xyz
+    res = ow.reconstruct(xyz, n, wl.box, w, ptab, "cic", 2, 1e-10, 5000)
+    ref = ow.split_cg(res["system"], res["b"], 1e-13, 20000)["x"]
+    ctx.set_grid(n, wl.box)
+    ctx.set_mask(w)
+    ctx.set_power(ptab)
+    ctx.set_galaxies(xyz)
+    ctx.deposit("cic", 2)
+    x, info = ctx.solve(precision="fp64", precond="prior", tol=1e-12, max_iter=20000)
+    assert info.status == WF_OK
+    assert rel_l2(x, ref) < 1e-9
+    y, info = ctx.solve(precision="mixed", precond="prior", tol=1e-9, max_iter=20000)
+    assert info.status == WF_OK
+    assert rel_l2(y, ref) < 300 * 1e-9
