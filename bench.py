@@ -68,7 +68,7 @@ def make_inputs(name, n_override=None):
     return wl, ptab, w, cat
 
 
-def cpu_baseline(wl, ptab, w, n_gal, iters_fp64, precond="none", sample_iters=3):
+def cpu_baseline(wl, ptab, w, n_gal, iters_fp64, precond="none", sample_iters=2):
     """The oracle's CG on the same system (plain, or on the prior-split system
     for precond="prior"), timed on the host cores over a few iterations and
     scaled to a whole FP64 solve of `iters_fp64` iterations."""
@@ -81,7 +81,7 @@ def cpu_baseline(wl, ptab, w, n_gal, iters_fp64, precond="none", sample_iters=3)
     solve = ow.split_cg if precond == "prior" else ow.cg
     name = "prior-split CG" if precond == "prior" else "plain-CG"
     with threadpool_limits(1):
-        solve(system, b, 0.0, 1)  # warm the FFT plan cache
+        solve(system, b, 0.0, 0)  # warm the FFT plan cache
         t0 = time.perf_counter()
         solve(system, b, 0.0, 0)  # the set-up and final residual, without iterations
         t1 = time.perf_counter()
@@ -97,7 +97,7 @@ def cpu_baseline(wl, ptab, w, n_gal, iters_fp64, precond="none", sample_iters=3)
     # cores (at most 16, the share of one GPU)
     workers = min(16, os.cpu_count() or 1)
     system_mt = ow.System(wl.n, wl.box, w, ptab, nbar, workers=workers)
-    solve(system_mt, b, 0.0, 1)
+    solve(system_mt, b, 0.0, 0)
     t0 = time.perf_counter()
     solve(system_mt, b, 0.0, 0)
     t1 = time.perf_counter()
