@@ -117,7 +117,7 @@ typedef struct wf_server wf_server;
  *   check_every host convergence checks every this many iterations (0: 16).
  *               Results do not depend on it: the device stops iterating at
  *               convergence by itself.
- *   precond     wf_precond (the stepwise solve supports WF_PRECOND_NONE only). */
+ *   precond     wf_precond. */
 typedef struct {
   wf_precision precision;
   double tol;
@@ -207,12 +207,15 @@ wf_status wf_forward_spectrum(wf_ctx* ctx, wf_precision prec, const double* v,
 wf_status wf_solve(wf_ctx* ctx, const wf_solve_opts* opts, double* s_out,
                    wf_mem mem, wf_solve_info* info);
 
-/* Krylov state of an FP64 solve, for checkpoint / resume.  wf_solve_begin
- * starts an FP64 solve, wf_solve_step runs up to `iters` iterations,
- * wf_solve_snapshot copies the state (x, r, p and scalars) into host_buf of
- * wf_snapshot_bytes() bytes, wf_solve_resume restores it into a context with
- * the same grid, mask, power and rhs, and wf_solve_finish writes s and info.
- * Continuing from a snapshot gives bit-identical results. */
+/* Krylov state of an FP64 solve (plain or prior-split), for checkpoint /
+ * resume.  wf_solve_begin starts an FP64 solve, wf_solve_step runs up to
+ * `iters` iterations, wf_solve_snapshot copies the state (x, r, p and scalars;
+ * half spectra for the prior-split form) into host_buf of wf_snapshot_bytes()
+ * bytes (the size for the active solve; without one, that of a plain solve),
+ * wf_solve_resume restores it into a context with the same grid, mask, power
+ * and rhs (the snapshot records its form), and wf_solve_finish writes s and
+ * info.  Continuing from a snapshot gives bit-identical results, equal to an
+ * uninterrupted wf_solve of as many iterations. */
 wf_status wf_solve_begin(wf_ctx* ctx, const wf_solve_opts* opts);
 wf_status wf_solve_step(wf_ctx* ctx, int32_t iters, int32_t* done);
 size_t wf_snapshot_bytes(const wf_ctx* ctx);

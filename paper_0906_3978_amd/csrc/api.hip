@@ -437,10 +437,9 @@ wf_status wf_solve_begin(wf_ctx* c, const wf_solve_opts* opts) {
                   "wf_solve_begin needs grid, mask, power and a data vector");
   if (!s.ok()) return finish(c, s);
   if (opts->precision != WF_FP64) return finish(c, fail(WF_EINVAL, "stepwise solves are FP64"));
-  if (opts->precond != WF_PRECOND_NONE)
-    return finish(c, fail(WF_EINVAL, "stepwise solves are not preconditioned"));
   s = validate_opts(*opts);
   if (s.ok()) s = set_device(c);
+  if (s.ok() && opts->precond == WF_PRECOND_PRIOR) s = ensure_split_fac(c->al, c->od, c->stream);
   if (s.ok()) s = fp64_begin(c->od, c->al, c->sw, c->nbar, *opts, c->stream);
   c->solve_active = s.ok();
   c->active_opts = *opts;
@@ -461,14 +460,15 @@ wf_status wf_solve_step(wf_ctx* c, int32_t iters, int32_t* done) {
 
 size_t wf_snapshot_bytes(const wf_ctx* c) {
   if (!c || !c->have_grid) return 0;
-  return snapshot_bytes(c->od.g);
+  return snapshot_bytes(c->od.g, c->solve_active && c->sw.split);
 }
 
 wf_status wf_solve_snapshot(wf_ctx* c, void* buf, size_t bytes) {
   if (!c || !buf) return c ? finish(c, fail(WF_EINVAL, "null buffer")) : WF_EINVAL;
   Status s = need(c->solve_active, "no active solve");
   if (!s.ok()) return finish(c, s);
-  if (bytes < snapshot_bytes(c->od.g)) return finish(c, fail(WF_EINVAL, "snapshot buffer too small"));
+  if (bytes < snapshot_bytes(c->od.g, c->sw.split))
+    return finish(c, fail(WF_EINVAL, "snapshot buffer too small"));
   s = set_device(c);
   if (s.ok()) s = snapshot_save(c->od.g, c->sw, buf, c->stream);
   return finish(c, s);
@@ -479,8 +479,12 @@ wf_status wf_solve_resume(wf_ctx* c, const void* buf, size_t bytes) {
   Status s = need(c->have_grid && c->have_mask && c->have_power && c->have_rhs,
                   "resume needs grid, mask, power and a data vector");
   if (!s.ok()) return finish(c, s);
-  if (bytes < snapshot_bytes(c->od.g)) return finish(c, fail(WF_EINVAL, "snapshot buffer too small"));
+  if (bytes < snapshot_bytes(c->od.g, false)) return finish(c, fail(WF_EINVAL, "snapshot buffer too small"));
+  const bool split = snapshot_split(buf);
+  if (bytes < snapshot_bytes(c->od.g, split))
+    return finish(c, fail(WF_EINVAL, "snapshot buffer too small"));
   s = set_device(c);
+  if (s.ok() && split) s = ensure_split_fac(c->al, c->od, c->stream);
   if (s.ok()) s = snapshot_load(c->od, c->al, c->sw, buf, c->stream);
   c->solve_active = s.ok();
   return finish(c, s);

@@ -36,12 +36,13 @@ Status solve_finish(const OperatorData& od, SolveWork& sw, int nr, bool mixed, h
 void solve_infos(const CgState* st, int nr, bool mixed, bool split, const Grid& g, double ms,
                  wf_solve_info* infos);
 
-// Stepwise FP64 solve of one RHS (checkpoint / resume).
+// Stepwise FP64 solve of one RHS (checkpoint / resume), plain or prior-split.
 Status fp64_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, double nbar,
                   const wf_solve_opts& o, hipStream_t s);
 Status fp64_iterations(const OperatorData& od, SolveWork& sw, int iters, hipStream_t s);
 Status fp64_finish(const OperatorData& od, SolveWork& sw, hipStream_t s, wf_solve_info* info);
-size_t snapshot_bytes(const Grid& g);
+size_t snapshot_bytes(const Grid& g, bool split);
+bool snapshot_split(const void* buf);  // header of a snapshot (at least its header's bytes)
 Status snapshot_save(const Grid& g, SolveWork& sw, void* buf, hipStream_t s);
 Status snapshot_load(const OperatorData& od, const Allocator& al, SolveWork& sw, const void* buf,
                      hipStream_t s);

@@ -323,35 +323,27 @@ Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
 
 Status fp64_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, double nbar,
                   const wf_solve_opts& o, hipStream_t s) {
-  WF_TRY(sw.ensure(al, od.g, 1, true, false));
+  WF_TRY(sw.ensure(al, od.g, 1, true, false, o.precond == WF_PRECOND_PRIOR));
   std::vector<CgState> st(1);
   st[0] = CgState{};
   st[0].nbar = nbar;
   st[0].tol = o.tol;
   st[0].max_iter = o.max_iter;
   WF_TRY(push_states(sw, st, s));
-  Vecs<double> v = v64(sw);
-  WF_HIP(launch_cg_init<double>(v.x, v.r, sw.b64.as<double>(), od.g.m, od.g.m,
-                                sw.partials.as<double>(), sw.state.as<CgState>(), 1, s));
-  return {};
+  return solve_start(od, sw, 1, false, s);
 }
 
 Status fp64_iterations(const OperatorData& od, SolveWork& sw, int iters, hipStream_t s) {
   Vecs<double> v = v64(sw);
-  for (int k = 0; k < iters; ++k) WF_TRY(cg_iteration<double>(od, sw, v, 1, s));
+  for (int k = 0; k < iters; ++k) WF_TRY(any_iteration<double>(od, sw, v, 1, s));
   return {};
 }
 
 Status fp64_finish(const OperatorData& od, SolveWork& sw, hipStream_t s, wf_solve_info* info) {
-  WF_TRY(true_residual(od, sw, sw.q64.as<double>(), 1, s));
+  WF_TRY(solve_finish(od, sw, 1, false, s));
   WF_TRY(sw.pull_state(s));
   const CgState& c = sw.st_host[0];
-  *info = wf_solve_info{};
-  info->iters_total = c.iter;
-  info->rel_res_recursive = c.bnorm > 0 ? c.rel : 0.0;
-  info->rel_res_true = c.bnorm > 0 ? std::sqrt(c.outer_rr) / c.bnorm : 0.0;
-  info->model_bytes = (c.iter * model_bytes_iteration(true) + model_bytes_residual()) * (double)od.g.m;
-  info->nbar = c.nbar;
+  solve_infos(sw.st_host, 1, false, sw.split, od.g, 0.0, info);
   info->status = c.done ? map_cg_status(c.status) : WF_ENOTCONV;
   if (info->status != WF_OK)
     return fail((wf_status)info->status, wf_status_str((wf_status)info->status));
@@ -362,24 +354,34 @@ namespace {
 struct SnapHeader {
   uint64_t magic;
   int32_t n;
-  int32_t pad;
+  int32_t split;  // 1: prior-split solve (x, r, p are half spectra)
   double box;
 };
 constexpr uint64_t SNAP_MAGIC = 0x5746534e41503031ull;  // "WFSNAP01"
 }  // namespace
 
-size_t snapshot_bytes(const Grid& g) {
-  return sizeof(SnapHeader) + sizeof(CgState) + 3 * (size_t)g.m * 8;
+static size_t vector_len(const Grid& g, bool split) {
+  return split ? 2 * (size_t)g.spec_total : (size_t)g.m;
+}
+
+size_t snapshot_bytes(const Grid& g, bool split) {
+  return sizeof(SnapHeader) + sizeof(CgState) + 3 * vector_len(g, split) * 8;
+}
+
+bool snapshot_split(const void* buf) {
+  SnapHeader h;
+  std::memcpy(&h, buf, sizeof h);
+  return h.magic == SNAP_MAGIC && h.split == 1;
 }
 
 Status snapshot_save(const Grid& g, SolveWork& sw, void* buf, hipStream_t s) {
   char* p = static_cast<char*>(buf);
-  SnapHeader h{SNAP_MAGIC, g.n, 0, g.box};
+  SnapHeader h{SNAP_MAGIC, g.n, sw.split ? 1 : 0, g.box};
   std::memcpy(p, &h, sizeof h);
   p += sizeof h;
   WF_HIP(hipMemcpyAsync(p, sw.state.p, sizeof(CgState), hipMemcpyDeviceToHost, s));
   p += sizeof(CgState);
-  const size_t vb = (size_t)g.m * 8;
+  const size_t vb = vector_len(g, sw.split) * 8;
   WF_HIP(hipMemcpyAsync(p, sw.x64.p, vb, hipMemcpyDeviceToHost, s));
   WF_HIP(hipMemcpyAsync(p + vb, sw.r64.p, vb, hipMemcpyDeviceToHost, s));
   WF_HIP(hipMemcpyAsync(p + 2 * vb, sw.p64.p, vb, hipMemcpyDeviceToHost, s));
@@ -392,16 +394,17 @@ Status snapshot_load(const OperatorData& od, const Allocator& al, SolveWork& sw,
   const char* p = static_cast<const char*>(buf);
   SnapHeader h;
   std::memcpy(&h, p, sizeof h);
-  if (h.magic != SNAP_MAGIC || h.n != od.g.n || h.box != od.g.box)
+  if (h.magic != SNAP_MAGIC || h.n != od.g.n || h.box != od.g.box || (h.split != 0 && h.split != 1))
     return fail(WF_EINVAL, "snapshot does not match this grid");
-  WF_TRY(sw.ensure(al, od.g, 1, true, false));
+  if (h.split && !od.fac_ready) return fail(WF_ESTATE, "prior-split factor not built");
+  WF_TRY(sw.ensure(al, od.g, 1, true, false, h.split == 1));
   p += sizeof h;
   CgState st;
   std::memcpy(&st, p, sizeof st);
   st.ticket = 0;
   WF_HIP(hipMemcpyAsync(sw.state.p, &st, sizeof st, hipMemcpyHostToDevice, s));
   p += sizeof(CgState);
-  const size_t vb = (size_t)od.g.m * 8;
+  const size_t vb = vector_len(od.g, h.split == 1) * 8;
   WF_HIP(hipMemcpyAsync(sw.x64.p, p, vb, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(sw.r64.p, p + vb, vb, hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(sw.p64.p, p + 2 * vb, vb, hipMemcpyHostToDevice, s));

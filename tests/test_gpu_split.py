@@ -190,7 +190,7 @@ def test_split_option_checks(ctx, bbks48):
     out = np.empty((48,) * 3)
     assert L.wf_solve(ctx._h, ctypes.byref(o), out.ctypes.data, 0, None) == WF_EINVAL
     with pytest.raises(wf.WienerError):
-        ctx.solve_begin(precision="fp64", precond="prior", tol=1e-8)
+        ctx.solve_begin(precision="mixed", precond="prior", tol=1e-8)
 
 
 @pytest.mark.parametrize("n", [8, 12, 16, 24, 64, 96])
@@ -215,3 +215,34 @@ def test_split_across_grid_sizes(ctx, n):
     y, info = ctx.solve(precision="mixed", precond="prior", tol=1e-9, max_iter=20000)
     assert info.status == WF_OK
     assert rel_l2(y, ref) < 300 * 1e-9
+
+
+def test_split_snapshot_resume_bit_identical(bbks48):
+    """The stepwise FP64 prior-split solve: a snapshot resumed in a new
+    context continues bit for bit, and equals an uninterrupted solve of as
+    many iterations."""
+    d = bbks48
+    a = context()
+    _load(a, d)
+    a.solve_begin(precision="fp64", precond="prior", tol=1e-12, max_iter=5000)
+    a.solve_step(25)
+    snap = a.snapshot()
+    a.solve_step(35)
+    x_direct, info_d = a.solve_finish(allow=(WF_OK, WF_ENOTCONV))
+    assert info_d.iters_total == 60
+    b = context()
+    _load(b, d)
+    b.resume(snap)
+    b.solve_step(35)
+    x_resumed, info_r = b.solve_finish(allow=(WF_OK, WF_ENOTCONV))
+    assert np.array_equal(x_direct, x_resumed)
+    assert info_r.rel_res_true == info_d.rel_res_true
+    x60, _ = a.solve(precision="fp64", precond="prior", tol=0.0, max_iter=60,
+                     allow=(WF_ENOTCONV,))
+    assert np.array_equal(x60, x_direct)
+    # a plain snapshot is smaller and resumes as a plain solve
+    a.solve_begin(precision="fp64", tol=1e-12, max_iter=5000)
+    a.solve_step(5)
+    assert a.snapshot().size < snap.size
+    a.close()
+    b.close()
