@@ -530,6 +530,18 @@ def main():
                  "rel_res_true": infp.rel_res_true,
                  "speedup_of_prior_split": round(tp / (info.time_ms * 1e-3), 3)}
         log(f"[bench] plain mixed solve {tp:.3f} s iters={infp.iters_total}")
+        # plain FP64 GPU CG (no preconditioning) to the same error target
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, inf64p = ctx.solve(out=out, precision="fp64", tol=TOLERANCES["none"], max_iter=100000,
+                              precond="none")
+        torch.cuda.synchronize()
+        t64p = time.perf_counter() - t
+        plain.update({"fp64_solve_s": round(t64p, 4), "fp64_iters": inf64p.iters_total,
+                      "fp64_rel_res_true": inf64p.rel_res_true,
+                      "speedup_mixed_prior_split_over_plain_fp64":
+                          round(t64p / (info.time_ms * 1e-3), 3)})
+        log(f"[bench] plain fp64 solve {t64p:.3f} s iters={inf64p.iters_total}")
 
     post = None
     if not args.no_post:
