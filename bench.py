@@ -391,7 +391,7 @@ def main():
         args.tol = TOLERANCES[args.precond]
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build measures one GPU: the Wiener solve of one grid "
+        print(json.dumps({"error": "bench.py measures one GPU: the Wiener solve of one grid "
                           "runs on a single MI355X; run with --gpus 1"}))
         sys.exit(2)
 
