@@ -21,7 +21,6 @@ template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
 template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
-template <typename V, typename T> __device__ __forceinline__ V cscale(V a, T s) { return {a.x * s, a.y * s}; }
 // multiply by -i (dir = -1) or +i (dir = +1)
 template <int DIR, typename V> __device__ __forceinline__ V mul_i(V a) {
   if constexpr (DIR < 0) return {a.y, -a.x};

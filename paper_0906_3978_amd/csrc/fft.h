@@ -176,19 +176,12 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* __res
   for (int i = threadIdx.x; i < N; i += NT) dst[i] = src[i];
 }
 
-// Element index (along the FFT axis) of value r of butterfly `bf` in the last
-// forward stage of a batch-fast tile; the same thread's values after that
-// stage are the inputs of the first inverse stage.
-template <int N, int NB> __device__ __forceinline__ int lam_stage_index(int bf, int r) {
-  constexpr int R = Plan<N>::r[Plan<N>::len - 1];
-  return bf / NB + r * (N / R);
-}
-
 // Forward FFT, multiply by a per-element diagonal, inverse FFT, on a
 // batch-fast tile.  The last forward stage, the diagonal and the first
 // inverse stage run on the same registers: that thread holds outputs
 // j + r N/R of the forward transform, exactly the inputs of its inverse
-// butterfly.  lamv[i][r] is the diagonal at element lam_stage_index(bf_i, r).
+// butterfly.  lamv[i][r] is the diagonal at element bf_i / NB + r N / R of
+// the FFT axis (bf_i the thread's i-th butterfly, R the last radix).
 template <typename T, int N, int NB, int NT>
 __device__ __forceinline__ void fft_tile_diag(cplx<T>* lds, const cplx<T>* __restrict__ tw,
                                               const T (*lamv)[Plan<N>::r[Plan<N>::len - 1]]) {

@@ -142,57 +142,6 @@ template hipError_t launch_cg_flush<float>(float*, const float*, int64_t, int64_
 template hipError_t launch_cg_flush<double>(double*, const double*, int64_t, int64_t, CgState*, int,
                                             hipStream_t);
 
-// CG direction on flat vectors (the prior-split solve, whose vectors live in
-// the half spectrum): the pending x += alpha p, then p = r + beta p.
-template <typename T>
-__global__ __launch_bounds__(VEC_THREADS) void k_cg_dir(T* x, T* p, const T* r, int64_t m,
-                                                        int64_t rs, const CgState* st_all) {
-  using R = typename Vec16<T>::type;
-  constexpr int RW = 16 / sizeof(T);
-  const int rhs = blockIdx.y;
-  const CgState* st = st_all + rhs;
-  if (st->done) return;
-  const bool first = st->first != 0, pending = st->pending != 0;
-  const T alpha = (T)st->alpha, beta = (T)st->beta;
-  T* xx = x + rhs * rs;
-  T* pp = p + rhs * rs;
-  const T* rr = r + rhs * rs;
-  const int64_t mv = m / RW;
-  const int64_t stride = (int64_t)gridDim.x * VEC_THREADS;
-  for (int64_t i = (int64_t)blockIdx.x * VEC_THREADS + threadIdx.x; i < mv; i += stride) {
-    R rv = __builtin_nontemporal_load(reinterpret_cast<const R*>(rr) + i);
-    if (!first) {
-      const R pv = __builtin_nontemporal_load(reinterpret_cast<const R*>(pp) + i);
-      if (pending) {
-        R* xp = reinterpret_cast<R*>(xx) + i;
-        __builtin_nontemporal_store(__builtin_nontemporal_load(xp) + alpha * pv, xp);
-      }
-      rv += beta * pv;
-    }
-    __builtin_nontemporal_store(rv, reinterpret_cast<R*>(pp) + i);
-  }
-  for (int64_t i = mv * RW + (int64_t)blockIdx.x * VEC_THREADS + threadIdx.x; i < m; i += stride) {
-    T v = rr[i];
-    if (!first) {
-      if (pending) xx[i] += alpha * pp[i];
-      v += beta * pp[i];
-    }
-    pp[i] = v;
-  }
-}
-
-template <typename T>
-hipError_t launch_cg_dir(T* x, T* p, const T* r, int64_t m, int64_t rs, const CgState* st,
-                         int nrhs, hipStream_t s) {
-  dim3 grid(vec_blocks(m), nrhs);
-  hipLaunchKernelGGL(k_cg_dir<T>, grid, dim3(VEC_THREADS), 0, s, x, p, r, m, rs, st);
-  return hipGetLastError();
-}
-template hipError_t launch_cg_dir<float>(float*, float*, const float*, int64_t, int64_t,
-                                         const CgState*, int, hipStream_t);
-template hipError_t launch_cg_dir<double>(double*, double*, const double*, int64_t, int64_t,
-                                          const CgState*, int, hipStream_t);
-
 __global__ __launch_bounds__(VEC_THREADS) void k_state_norm(const double* v, int64_t m, int64_t rs,
                                                             double* partials, CgState* st_all) {
   __shared__ double red[VEC_THREADS / 64];

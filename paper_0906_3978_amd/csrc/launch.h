@@ -189,10 +189,6 @@ hipError_t launch_xlam_rows(int n, const double* lam, double* rows64, float* row
 int64_t split_fac_elems(int n);
 hipError_t launch_split_fac(int n, const double* lam, double m_cells, double* fac64, float* fac32,
                             hipStream_t s);
-// CG direction on flat vectors: (pending) x += alpha p; p = r + beta p (p = r first)
-template <typename T> hipError_t launch_cg_dir(T* x, T* p, const T* r, int64_t m,
-                                               int64_t rhs_stride, const CgState* st, int nrhs,
-                                               hipStream_t s);
 // onorm = ||v|| per RHS
 hipError_t launch_state_norm(const double* v, int64_t m, int64_t rhs_stride, double* partials,
                              CgState* st, int nrhs, hipStream_t s);
