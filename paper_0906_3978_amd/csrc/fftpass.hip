@@ -1013,7 +1013,8 @@ hipError_t launch_xlam_rows(int n, const double* lam, double* rows64, float* row
   return hipGetLastError();
 }
 
-// Strided tiles: TB = str_tb<T, N> adjacent columns, 512 threads.
+// Strided tiles: TB = str_tb<T, N> adjacent columns, 512 threads (1024 for
+// some FP32 passes, see strided_n).
 constexpr int NT_STRIDED = 512;
 
 int strided_tb(int n, bool fp64) {
@@ -1121,8 +1122,15 @@ static hipError_t strided_v(int mode, const StrArgs<T>& a, int nrhs, hipStream_t
   return hipGetLastError();
 }
 
+// FP32 tiles of the large grids run 1024 threads (four 16-byte loads per
+// thread and array instead of eight, one block of 16 waves per CU instead of
+// two of 8): at 512^3 the y passes and the x inverse with the CG direction
+// are 3-4 % faster; the x forward with q is not, and keeps 512.
 template <typename T, int N>
 static hipError_t strided_n(int mode, const StrArgs<T>& a, int nrhs, hipStream_t s) {
+  if constexpr (sizeof(T) == 4 && N >= 256) {
+    if (mode != SM_FWD_CGQ) return strided_v<T, N, str_tb<T, N>(), 1024>(mode, a, nrhs, s);
+  }
   return strided_v<T, N, str_tb<T, N>(), NT_STRIDED>(mode, a, nrhs, s);
 }
 
