@@ -31,12 +31,20 @@ from .wiener import m2_half_grid
 
 def rsd_factor(k, beta, sigma):
     """<K D>_mu(k): int_0^1 (1 + beta mu^2)^2 / (1 + k^2 sigma^2 mu^2 / 2) dmu
-    (Kaiser factor times the Lorentzian damping, angle averaged)."""
+    (Kaiser factor times the Lorentzian damping, angle averaged).  For
+    a = k^2 sigma^2 / 2 > 1 the same integral is taken in t = sqrt(a) mu,
+    (1 / sqrt(a)) int_0^sqrt(a) (1 + beta t^2 / a)^2 / (1 + t^2) dt, where the
+    Lorentzian has unit width and the quadrature reaches its tolerance."""
     def one(kk):
         a = 0.5 * kk * kk * sigma * sigma
-        val, _ = integrate.quad(lambda mu: (1 + beta * mu * mu) ** 2 / (1 + a * mu * mu), 0.0, 1.0,
+        if a <= 1.0:
+            val, _ = integrate.quad(lambda mu: (1 + beta * mu * mu) ** 2 / (1 + a * mu * mu),
+                                    0.0, 1.0, epsabs=0.0, epsrel=2e-14, limit=200)
+            return val
+        ra = math.sqrt(a)
+        val, _ = integrate.quad(lambda t: (1 + beta * t * t / a) ** 2 / (1 + t * t), 0.0, ra,
                                 epsabs=0.0, epsrel=2e-14, limit=200)
-        return val
+        return val / ra
     return np.array([one(float(kk)) for kk in np.atleast_1d(k)])
 
 

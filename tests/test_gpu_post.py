@@ -28,7 +28,7 @@ def _setup(ctx, n, box, seed=1):
     return w
 
 
-@pytest.mark.parametrize("n,box", [(32, 500.0), (24, 300.0)])
+@pytest.mark.parametrize("n,box", [(32, 500.0), (24, 300.0), (128, 100.0)])
 def test_rsd_factor(ctx, n, box):
     _setup(ctx, n, box)
     got = ctx.rsd_factor(BETA, SIGMA)
