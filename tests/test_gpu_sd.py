@@ -194,3 +194,26 @@ def test_sd_without_galaxies_is_zero(ctx, sd32):
                                        tol=1e-8, max_iter=100)
         assert not mean.any() and not xs.any()
         assert all(i.status == WF_OK and i.iters_total == 0 for i in infos)
+
+
+def test_sd_and_post_with_device_buffers(ctx, sd32):
+    """The same calls with device (torch) buffers give the host-buffer results
+    bit for bit."""
+    import torch
+    d = sd32
+    _load(ctx, d)
+    kw = dict(precision="mixed", precond="prior", tol=1e-8, max_iter=20000)
+    mean_h, xs_h, _ = ctx.solve_sd("jackknife", alpha=d["alpha"], seed=3, nsamples=2,
+                                   keep_samples=True, **kw)
+    dev = torch.device("cuda:0")
+    mean_d = torch.empty(mean_h.shape, dtype=torch.float64, device=dev)
+    _, xs_d, _ = ctx.solve_sd("jackknife", alpha=d["alpha"], seed=3, nsamples=2,
+                              mean_out=mean_d, keep_samples=True, **kw)
+    assert np.array_equal(mean_d.cpu().numpy(), mean_h)
+    assert np.array_equal(xs_d.cpu().numpy(), xs_h)
+    sm_h = ctx.fourier_filter(mean_h, "gauss", a=6.0)
+    sm_d = ctx.fourier_filter(mean_d, "gauss", a=6.0)
+    assert np.array_equal(sm_d.cpu().numpy(), sm_h)
+    assert ctx.field_moments(sm_d, masked=True) == ctx.field_moments(sm_h, masked=True)
+    assert np.array_equal(ctx.compare_fields(sm_d, mean_d), ctx.compare_fields(sm_h, mean_h),
+                          equal_nan=True)
