@@ -34,7 +34,7 @@ def full():
     ctx.set_power(ptab)
     ctx.set_galaxies(cat.xyz)
     ctx.deposit(wl.scheme, wl.supersample)
-    yield dict(ctx=ctx, ref=ref, meta=meta)
+    yield dict(ctx=ctx, ref=ref, meta=meta, wl=wl, xyz=cat.xyz)
     ctx.close()
 
 
@@ -64,3 +64,32 @@ def test_fp64_solve_error_at_512(full):
     print(f"512^3 fp64 prior tol 1e-10: iters {info.iters_total} sampled rel L2 error {err:.3e}")
     # the reference is stored in float32 (relative rounding 6e-8 per value)
     assert err < 2e-7
+
+
+def test_deposit_at_512_sampled(full):
+    """The benchmark's deposit (TSC on the 1024^3 grid) at full size: the
+    int64 grid, bit for bit, at the stencil nodes of 2000 galaxies and at 4000
+    random nodes, against the oracle evaluating those nodes one by one; and
+    the exact total mass."""
+    import torch
+    import paper_0906_3978_amd as wf
+    from oracle import deposit as od
+    wl, xyz = full["wl"], full["xyz"]
+    nf = wl.supersample * wl.n
+    g = torch.empty((nf, nf, nf), dtype=torch.int64, device="cuda:0")
+    rc = wf.lib().wf_get_deposit(full["ctx"]._h, g.data_ptr(), None, None, 1)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(g.sum().item()) == len(xyz) * (1 << 39)
+    rng = np.random.Generator(np.random.PCG64(12))
+    pick = xyz[rng.choice(len(xyz), 2000, replace=False)]
+    near = np.floor(pick * (nf / wl.box) + 0.5).astype(np.int64)
+    offs = np.array([(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+    nodes = (near[:, None, :] + offs[None, :, :]).reshape(-1, 3) % nf
+    nodes = np.concatenate([nodes, rng.integers(0, nf, size=(4000, 3))])
+    nodes = np.unique(nodes, axis=0)
+    flat = (nodes[:, 0] * nf + nodes[:, 1]) * nf + nodes[:, 2]
+    got = g.view(-1)[torch.from_numpy(flat).to(g.device)].cpu().numpy()
+    want = od.deposit_at(xyz, nf, wl.box, wl.scheme, nodes)
+    print(f"1024^3 deposit: {len(nodes)} nodes, {int((want != 0).sum())} non-zero")
+    assert np.array_equal(got, want)
