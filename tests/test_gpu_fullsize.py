@@ -93,3 +93,27 @@ def test_deposit_at_512_sampled(full):
     want = od.deposit_at(xyz, nf, wl.box, wl.scheme, nodes)
     print(f"1024^3 deposit: {len(nodes)} nodes, {int((want != 0).sum())} non-zero")
     assert np.array_equal(got, want)
+
+
+def test_observed_counts_at_512_sampled(full):
+    """n^o of the same step (the 1024^3 grid low-passed to 512^3) at 40 target
+    cells against the oracle's direct summation over every galaxy's stencil
+    (no FFT on that side)."""
+    import torch
+    import paper_0906_3978_amd as wf
+    from oracle import supersample as oss
+    wl, xyz = full["wl"], full["xyz"]
+    n = wl.n
+    nobs = torch.empty((n, n, n), dtype=torch.float64, device="cuda:0")
+    rc = wf.lib().wf_get_deposit(full["ctx"]._h, None, nobs.data_ptr(), None, 1)
+    assert rc == 0
+    rng = np.random.Generator(np.random.PCG64(13))
+    near = np.floor(xyz[rng.choice(len(xyz), 20, replace=False)] * (n / wl.box) + 0.5)
+    cells = np.concatenate([near.astype(np.int64) % n, rng.integers(0, n, size=(20, 3))])
+    flat = (cells[:, 0] * n + cells[:, 1]) * n + cells[:, 2]
+    got = nobs.view(-1)[torch.from_numpy(flat).to(nobs.device)].cpu().numpy()
+    want = oss.observed_counts_at(xyz, n, wl.box, wl.scheme, cells)
+    scale = float(np.abs(want).max())
+    print(f"512^3 n_obs at 40 cells: max |got - want| / max |want| = "
+          f"{np.abs(got - want).max() / scale:.2e}")
+    assert np.abs(got - want).max() <= 1e-11 * scale
