@@ -171,6 +171,37 @@ def _ptr(a):
     raise TypeError(f"unsupported array type {type(a)}")
 
 
+_DTYPES = {"f64": (np.float64, "float64"), "i64": (np.int64, "int64"),
+           "i32": (np.int32, "int32")}
+
+
+def _arg(a, kind, count, what, device=None):
+    """(pointer, mem) of an array the library reads or writes as `count`
+    elements of `kind` ("f64", "i64", "i32"): a numpy array, or a torch tensor
+    (on `device` when it is a GPU tensor).  The library trusts the sizes its
+    arguments imply, so a wrong dtype, size or device is refused here, before
+    any call into it."""
+    if a is None:
+        return None, WF_HOST
+    np_t, torch_name = _DTYPES[kind]
+    if isinstance(a, np.ndarray):
+        if a.dtype != np_t:
+            raise TypeError(f"{what}: dtype {a.dtype}, expected {torch_name}")
+        numel = a.size
+    elif hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        if str(a.dtype) != "torch." + torch_name:
+            raise TypeError(f"{what}: dtype {a.dtype}, expected torch.{torch_name}")
+        if a.is_cuda and device is not None and a.device.index != device:
+            raise ValueError(f"{what}: tensor on cuda:{a.device.index}, the context is on "
+                             f"cuda:{device}")
+        numel = a.numel()
+    else:
+        raise TypeError(f"{what}: unsupported array type {type(a)}")
+    if count is not None and numel != count:
+        raise ValueError(f"{what}: {numel} elements, expected {count}")
+    return _ptr(a)
+
+
 def _torch_allocator(device):
     import torch
 
@@ -265,19 +296,26 @@ class Context:
         self._check(self._L.wf_set_grid(self._h, int(n), float(box)))
         self.n, self.box = int(n), float(box)
 
+    def _m(self):
+        if self.n is None:
+            raise WienerError(2, "set_grid first")
+        return self.n ** 3
+
     def set_mask(self, w):
         w = _as_f64(w)
-        p, mem = _ptr(w)
+        p, mem = _arg(w, "f64", self._m(), "mask", self.device)
         self._check(self._L.wf_set_mask(self._h, p, mem))
 
     def set_power(self, p_by_m2):
         a = _as_f64(p_by_m2)
-        p, mem = _ptr(a)
+        p, mem = _arg(a, "f64", None, "p_by_m2", self.device)
         self._check(self._L.wf_set_power(self._h, p, int(_numel(a)), mem))
 
     def set_galaxies(self, xyz):
         a = _as_f64(xyz)
-        p, mem = _ptr(a)
+        if _numel(a) % 3:
+            raise ValueError("xyz: the element count must be a multiple of 3")
+        p, mem = _arg(a, "f64", None, "xyz", self.device)
         self._check(self._L.wf_set_galaxies(self._h, p, int(_numel(a) // 3), mem))
 
     def deposit(self, scheme="cic", supersample=1):
@@ -294,11 +332,12 @@ class Context:
 
     def set_rhs(self, b, nbar):
         b = _as_f64(b)
-        p, mem = _ptr(b)
+        p, mem = _arg(b, "f64", self._m(), "b", self.device)
         self._check(self._L.wf_set_rhs(self._h, p, float(nbar), mem))
 
     def apply_operator(self, v, precision="fp64"):
         v = np.ascontiguousarray(v, dtype=np.float64)
+        _arg(v, "f64", self._m(), "v")
         out = np.empty_like(v)
         self._check(self._L.wf_apply_operator(self._h, PRECISIONS[precision], _ptr(v)[0],
                                               _ptr(out)[0], WF_HOST))
@@ -306,6 +345,7 @@ class Context:
 
     def forward_spectrum(self, v, precision="fp64"):
         v = np.ascontiguousarray(v, dtype=np.float64)
+        _arg(v, "f64", self._m(), "v")
         n = self.n
         out = np.empty((n, n, n // 2 + 1), dtype=np.complex128)
         self._check(self._L.wf_forward_spectrum(self._h, PRECISIONS[precision], _ptr(v)[0],
@@ -326,28 +366,37 @@ class Context:
         """F^-1 diag(h) F v; kind "gauss" (a = r_S), "rsd_deconv" (a = beta,
         b = sigma, c = bias) or "table" (h by |m|^2)."""
         kinds = {"gauss": 0, "rsd_deconv": 1, "table": 2}
-        p, mem = _ptr(v)
+        m = self._m()
+        p, mem = _arg(v, "f64", m, "v", self.device)
         if out is None:
             out = np.empty(v.shape, dtype=np.float64) if mem == WF_HOST else v.new_empty(v.shape)
+        po, mo = _arg(out, "f64", m, "out", self.device)
+        if mo != mem:
+            raise ValueError("v and out must both be host arrays or both device tensors")
         tp, tl = (None, 0)
         if table is not None:
             table = _as_f64(table) if mem == WF_HOST else table
-            tp, tl = _ptr(table)[0], int(_numel(table))
+            tp, tm = _arg(table, "f64", None, "table", self.device)
+            if tm != mem:
+                raise ValueError("table must live where v does")
+            tl = int(_numel(table))
         self._check(self._L.wf_fourier_filter(self._h, kinds[kind], float(a), float(b), float(c),
-                                              tp, tl, p, _ptr(out)[0], mem))
+                                              tp, tl, p, po, mem))
         return out
 
     def field_moments(self, v, masked=False):
         """(count, mean, variance, skewness, excess kurtosis) over all cells or w > 0."""
-        p, mem = _ptr(v)
+        p, mem = _arg(v, "f64", self._m(), "v", self.device)
         out = np.empty(5, dtype=np.float64)
         self._check(self._L.wf_field_moments(self._h, p, int(bool(masked)), out.ctypes.data, mem))
         return tuple(float(x) for x in out)
 
     def compare_fields(self, rec, truth, masked=False):
         """(r, D_Euc, D_KL) between a reconstruction and a reference field."""
-        pr, mem = _ptr(rec)
-        pt, _ = _ptr(truth)
+        pr, mem = _arg(rec, "f64", self._m(), "rec", self.device)
+        pt, mt = _arg(truth, "f64", self._m(), "truth", self.device)
+        if mt != mem:
+            raise ValueError("rec and truth must both be host arrays or both device tensors")
         out = np.empty(3, dtype=np.float64)
         self._check(self._L.wf_compare_fields(self._h, pr, pt, int(bool(masked)), out.ctypes.data,
                                               mem))
@@ -358,7 +407,7 @@ class Context:
         n = self.n
         if out is None:
             out = np.empty((n, n, n), dtype=np.float64)
-        p, mem = _ptr(out)
+        p, mem = _arg(out, "f64", self._m(), "out", self.device)
         self._check(self._L.wf_inverse_weighting(self._h, SCHEMES[scheme], int(supersample), p, mem))
         return out
 
@@ -368,7 +417,7 @@ class Context:
         n = self.n
         if out is None:
             out = np.empty((n, n, n), dtype=np.float64)
-        p, mem = _ptr(out)
+        p, mem = _arg(out, "f64", self._m(), "out", self.device)
         si = SolveInfo()
         code = self._L.wf_solve(self._h, C.byref(o), p, mem, C.byref(si))
         self._check(code, ok=allow)
@@ -416,7 +465,18 @@ class Context:
         n = self.n
         if outs is None:
             outs = [np.empty((n, n, n), dtype=np.float64) for _ in range(nr)]
+        m = self._m()
         mem = _ptr(cats[0])[1] if nr else WF_HOST
+        for i, c in enumerate(cats):
+            if _numel(c) % 3:
+                raise ValueError(f"catalogue {i}: the element count must be a multiple of 3")
+            if _arg(c, "f64", None, f"catalogue {i}", self.device)[1] != mem:
+                raise ValueError("catalogues must all be host arrays or all device tensors")
+        if len(outs) != nr:
+            raise ValueError(f"{len(outs)} outputs for {nr} catalogues")
+        for i, x in enumerate(outs):
+            if _arg(x, "f64", m, f"output {i}", self.device)[1] != mem:
+                raise ValueError("outputs must live where the catalogues do")
         xp = (C.c_void_p * nr)(*[_ptr(c)[0] for c in cats])
         ng = (C.c_int64 * nr)(*[int(_numel(c) // 3) for c in cats])
         op = (C.c_void_p * nr)(*[_ptr(x)[0] for x in outs])
@@ -433,7 +493,7 @@ class Context:
         n = self.n
         if out is None:
             out = np.empty((count, n, n, n), dtype=np.int32)
-        p, mem = _ptr(out)
+        p, mem = _arg(out, "i32", int(count) * self._m(), "out", self.device)
         self._check(self._L.wf_jackknife_counts(self._h, float(alpha), int(seed), int(first),
                                                 int(count), p, mem))
         return out
@@ -448,11 +508,16 @@ class Context:
         kinds = {"mean": 1, "jackknife": 2}
         if mean_out is None:
             mean_out = np.empty((n, n, n), dtype=np.float64)
-        p, mem = _ptr(mean_out)
+        p, mem = _arg(mean_out, "f64", self._m(), "mean_out", self.device)
         if samples_out is None and keep_samples:
             samples_out = (np.empty((nsamples, n, n, n), dtype=np.float64) if mem == WF_HOST
                            else mean_out.new_empty((nsamples, n, n, n)))
-        sp = _ptr(samples_out)[0] if samples_out is not None else None
+        sp = None
+        if samples_out is not None:
+            sp, sm = _arg(samples_out, "f64", int(nsamples) * self._m(), "samples_out",
+                          self.device)
+            if sm != mem:
+                raise ValueError("samples_out must live where mean_out does")
         infos = (SolveInfo * nsamples)()
         code = self._L.wf_solve_sd(self._h, C.byref(o), kinds[kind], float(alpha), int(seed),
                                    int(first), int(nsamples), p, sp, mem, infos)
@@ -495,15 +560,24 @@ class Server:
         if code != WF_OK:
             raise WienerError(code, L.wf_status_str(code).decode())
         self._h = h
+        self._grid = {}   # ticket -> grid size of the request
 
     def _err(self, code):
         msg = self._L.wf_server_last_error(self._h)
         raise WienerError(code, msg.decode() if msg else "")
 
     def submit(self, n, box, w, p_by_m2, xyz, scheme="cic", supersample=2, **kw):
+        n = int(n)
         w = np.ascontiguousarray(w, dtype=np.float64)
         p = np.ascontiguousarray(p_by_m2, dtype=np.float64)
-        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        if w.size != n ** 3:
+            raise ValueError(f"w: {w.size} elements, expected {n ** 3}")
+        if p.size != 3 * (n // 2) ** 2 + 1:
+            raise ValueError(f"p_by_m2: {p.size} elements, expected {3 * (n // 2) ** 2 + 1}")
+        if xyz.size % 3:
+            raise ValueError("xyz: the element count must be a multiple of 3")
+        xyz = xyz.reshape(-1, 3)
         req = Request(int(n), float(box), w.ctypes.data, p.ctypes.data,
                       xyz.ctypes.data if len(xyz) else None, len(xyz), SCHEMES[scheme],
                       int(supersample), opts(**kw))
@@ -511,6 +585,7 @@ class Server:
         code = self._L.wf_server_submit(self._h, C.byref(req), C.byref(t))
         if code != WF_OK:
             self._err(code)
+        self._grid[int(t.value)] = n
         return int(t.value)
 
     def poll(self, ticket):
@@ -521,9 +596,19 @@ class Server:
             self._err(code)
         return bool(d.value), (_info(si) if d.value else None)
 
-    def fetch(self, ticket, n, allow=(WF_OK,)):
-        out = np.empty((n, n, n), dtype=np.float64)
+    def fetch(self, ticket, n=None, allow=(WF_OK,)):
+        """The result of a finished request (n^3 doubles, n the request's grid)."""
+        g = self._grid.get(ticket)
+        if g is None:
+            raise ValueError(f"unknown ticket {ticket}")
+        if n is not None and int(n) != g:
+            raise ValueError(f"ticket {ticket} is a {g}^3 request, not {n}^3")
+        done, _ = self.poll(ticket)
+        if not done:
+            raise WienerError(2, f"request {ticket} not finished")
+        out = np.empty((g, g, g), dtype=np.float64)
         code = self._L.wf_server_fetch(self._h, ticket, out.ctypes.data)
+        self._grid.pop(ticket, None)   # a finished ticket is released by the fetch
         if code not in allow:
             self._err(code)
         return out
