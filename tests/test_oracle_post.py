@@ -59,6 +59,51 @@ def test_gauss_filter_keeps_the_mean_and_smooths_a_spike():
     assert np.unravel_index(np.argmax(out), out.shape) == (5, 6, 7)
 
 
+def _rsd_closed_form(k, beta, sigma):
+    """<K D>_mu by polynomial division of the integrand: with a = k^2 sigma^2
+    / 2, (1 + beta mu^2)^2 = (1 + a mu^2)(A mu^2 + B) + C with A = beta^2 / a,
+    B = (2 beta - A) / a, C = 1 - B, so the mu-average over [0, 1] is
+    A / 3 + B + C atan(sqrt(a)) / sqrt(a)."""
+    a = 0.5 * k * k * sigma * sigma
+    A = beta * beta / a
+    B = (2 * beta - A) / a
+    C = 1.0 - B
+    return A / 3 + B + C * math.atan(math.sqrt(a)) / math.sqrt(a)
+
+
+@pytest.mark.parametrize("k", [0.08, 0.5, 3.0])
+def test_rsd_factor_closed_form(k):
+    beta, sigma = 0.42, 6.85
+    assert op.rsd_factor(np.array([k]), beta, sigma)[0] == pytest.approx(
+        _rsd_closed_form(k, beta, sigma), rel=1e-12)
+
+
+@pytest.mark.parametrize("n,box", [(8, 100.0), (24, 300.0), (32, 500.0), (128, 100.0)])
+def test_rsd_factor_table_quadrature_is_quiet(n, box):
+    """The factor tables of the GPU tests' grids, with every warning an
+    error (the quadrature must reach its accuracy without complaint)."""
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        op.rsd_factor_table(n, box, 0.24 ** 0.6, 500.0 / 73.0)
+
+
+@pytest.mark.parametrize("m", [(3, 1, 2), (0, -5, 4), (7, 7, 0)])
+def test_deconvolution_on_a_fourier_mode(m):
+    """A single mode through the eq:DEC filter with beta, sigma != 0 comes
+    out scaled by 1 / (b sqrt(<K D>_mu(k))) at k = (2 pi / L) |m|: pins the
+    k lattice of the tables and the factor away from every limit."""
+    n, box, beta, sigma, bias = 16, 120.0, 0.42, 6.85, 1.3
+    v = _cos_mode(n, m)
+    k = 2 * math.pi / box * math.sqrt(sum(c * c for c in m))
+    h = 1.0 / (bias * math.sqrt(_rsd_closed_form(k, beta, sigma)))
+    got = op.fourier_filter(v, op.deconv_table(n, box, beta, sigma, bias))
+    assert np.allclose(got, h * v, rtol=0, atol=1e-13)
+    # and the redshift-space prior factor of the same mode, straight from the table
+    tab = op.rsd_factor_table(n, box, beta, sigma)
+    assert tab[sum(c * c for c in m)] == pytest.approx(_rsd_closed_form(k, beta, sigma), rel=1e-12)
+
+
 def test_deconvolution_reduces_to_the_bias():
     n, box = 16, 100.0
     v = np.random.Generator(np.random.PCG64(1)).standard_normal((n, n, n))
