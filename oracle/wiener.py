@@ -99,20 +99,23 @@ class System:
         return self._irfft(self._rfft(r) / d)
 
 
-def cg(system, b, tol, max_iter, record=None):
+def cg(system, b, tol, max_iter, record=None, keep=()):
     """Plain conjugate gradients (Hestenes-Stiefel) from x_0 = 0.
 
     Stops after the first iteration whose recursive residual satisfies
     ||r|| / ||b|| <= tol, or after max_iter iterations.  Returns a dict with
     x, iterations, the recursive and true relative residuals, a status string
-    and the CG coefficients (for Lanczos estimates).
+    and the CG coefficients (for Lanczos estimates); `kept` maps every
+    iteration count listed in `keep` that was reached to a copy of that
+    iterate (an observation only: the arithmetic is the same with or without).
     """
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b)
     bnorm = math.sqrt(float(np.vdot(b, b)))
+    kept = {}
     if bnorm == 0.0:
         return dict(x=x, iterations=0, rel_res=0.0, rel_res_true=0.0,
-                    status="ok", alphas=[], betas=[])
+                    status="ok", alphas=[], betas=[], kept=kept)
     r = b.copy()
     p = r.copy()
     rho = float(np.vdot(r, r))
@@ -135,6 +138,8 @@ def cg(system, b, tol, max_iter, record=None):
         rel = math.sqrt(rho_new) / bnorm
         if record is not None:
             record.append(rel)
+        if it in keep:
+            kept[it] = x.copy()
         if rel <= tol:
             status = "ok"
             break
@@ -145,7 +150,7 @@ def cg(system, b, tol, max_iter, record=None):
     rt = b - system.apply(x)
     return dict(x=x, iterations=it, rel_res=rel,
                 rel_res_true=math.sqrt(float(np.vdot(rt, rt))) / bnorm,
-                status=status, alphas=alphas, betas=betas)
+                status=status, alphas=alphas, betas=betas, kept=kept)
 
 
 def pcg(system, b, tol, max_iter):

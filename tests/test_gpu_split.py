@@ -8,6 +8,7 @@ import synth
 from oracle import wiener as ow
 
 from gpu_util import context, rel_l2
+import sensitivity as se
 
 pytestmark = pytest.mark.gpu
 
@@ -43,13 +44,14 @@ def _load(ctx, d):
     ctx.deposit("cic", 2)
 
 
-@pytest.mark.parametrize("k,tol", [(1, 1e-13), (20, 1e-8), (80, 1e-7), (200, 1e-12)])
-def test_fixed_iteration_parity_split_fp64(ctx, bbks48, k, tol):
+@pytest.mark.parametrize("k", [1, 20, 80, 200])
+def test_fixed_iteration_parity_split_fp64(ctx, bbks48, k):
     """Both sides run exactly k iterations of CG on C A C from y = 0.  The
-    tolerance is ten times the oracle's own spread at that k: with 1e-16
-    relative noise added to each operator application its iterates move by
-    7.8e-10 at k = 20, 1.1e-8 at k = 80 (the phase where the large
-    eigenvalues are being resolved) and 2e-14 at k = 200."""
+    bound is a multiple of the oracle's own spread at that k under
+    rounding-sized noise (tests/sensitivity.py): its iterates move by 1.4e-9
+    at k = 20, 1.7e-8 at k = 80 (the phase where the large eigenvalues are
+    being resolved) and 3e-14 at k = 200."""
+    tol = se.bound("bbks48", "split", k)
     d = bbks48
     _load(ctx, d)
     x, info = ctx.solve(precision="fp64", precond="prior", tol=0.0, max_iter=k,
@@ -57,8 +59,9 @@ def test_fixed_iteration_parity_split_fp64(ctx, bbks48, k, tol):
     assert info.iters_total == k and info.status == WF_ENOTCONV
     ref = ow.split_cg(d["res"]["system"], d["res"]["b"], 0.0, k)
     err = rel_l2(x, ref["x"])
-    print(f"split fixed k={k}: rel_l2 {err:.3e} rec {info.rel_res_recursive:.6e} "
-          f"vs {ref['rel_res']:.6e}")
+    print(f"split fixed k={k}: rel_l2 {err:.3e} bound {tol:.1e} "
+          f"({err / max(se.SPREADS[('bbks48', 'split', k)], 1e-300):.2f} x the oracle's spread) "
+          f"rec {info.rel_res_recursive:.6e} vs {ref['rel_res']:.6e}")
     assert err < tol
     # residuals relative to ||C b|| and ||b||: their spread follows the iterates'
     assert abs(info.rel_res_recursive - ref["rel_res"]) < max(1e-12, tol)
