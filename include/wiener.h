@@ -308,6 +308,18 @@ wf_status wf_fourier_filter(wf_ctx* ctx, int32_t kind, double a, double b, doubl
 wf_status wf_field_moments(wf_ctx* ctx, const double* v, int32_t masked, double* out5,
                            wf_mem mem);
 
+/* wf_field_moments for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same summation order, so the same bits, but the
+ * block partials live in a static device array of 1024 x 5 + 8 doubles
+ * (41 KB per GPU, held until the process ends) instead of a buffer from the
+ * context's allocator; nothing is allocated.  v must be device memory on the
+ * context's GPU (n^3 doubles; host memory: WF_EINVAL), out5 host memory.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (several threads, several contexts) race and must be serialised by the
+ * caller.  Synchronises the context's stream. */
+wf_status wf_field_moments_noalloc(wf_ctx* ctx, const double* v, int32_t masked, double* out5);
+
 /* Quality measures of Sec. 4.1 between a reconstruction and a reference
  * field (n^3 each, over all cells or those with w > 0): out[0] = the
  * correlation coefficient r, out[1] = the Euclidean distance D_Euc,

@@ -116,6 +116,7 @@ SIGNATURES = {
     "wf_fourier_filter": (C.c_int, [_V, _I32, C.c_double, C.c_double, C.c_double, _P, C.c_int64,
                                     _P, _P, C.c_int]),
     "wf_field_moments": (C.c_int, [_V, _P, _I32, _P, C.c_int]),
+    "wf_field_moments_noalloc": (C.c_int, [_V, _P, _I32, _P]),
     "wf_compare_fields": (C.c_int, [_V, _P, _P, _I32, _P, C.c_int]),
     "wf_inverse_weighting": (C.c_int, [_V, C.c_int, _I32, _P, C.c_int]),
     "wf_jackknife_counts": (C.c_int, [_V, _D, C.c_uint64, C.c_int64, _I32, _P, C.c_int]),
@@ -389,6 +390,18 @@ class Context:
         p, mem = _arg(v, "f64", self._m(), "v", self.device)
         out = np.empty(5, dtype=np.float64)
         self._check(self._L.wf_field_moments(self._h, p, int(bool(masked)), out.ctypes.data, mem))
+        return tuple(float(x) for x in out)
+
+    def field_moments_noalloc(self, v, masked=False):
+        """field_moments of a device tensor through the allocation-free entry
+        point (its partials in a static device array shared by every call on
+        the GPU)."""
+        p, mem = _arg(v, "f64", self._m(), "v", self.device)
+        if mem != WF_DEVICE:
+            raise ValueError("v must be a GPU tensor")
+        out = np.empty(5, dtype=np.float64)
+        self._check(self._L.wf_field_moments_noalloc(self._h, p, int(bool(masked)),
+                                                     out.ctypes.data))
         return tuple(float(x) for x in out)
 
     def compare_fields(self, rec, truth, masked=False):

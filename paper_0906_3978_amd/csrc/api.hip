@@ -727,22 +727,31 @@ wf_status wf_field_moments(wf_ctx* c, const double* v, int32_t masked, double* o
     double sm[5];
     WF_TRY(field_sums(src, masked ? c->od.w64.as<double>() : nullptr, g.m, c->mpartials, c->al, sm,
                       c->stream));
-    const double n = sm[0];
-    double res[5] = {n, NAN, NAN, NAN, NAN};
-    if (n > 0) {
-      const double mu = sm[1] / n;
-      const double e2 = sm[2] / n, e3 = sm[3] / n, e4 = sm[4] / n;
-      const double var = e2 - mu * mu;
-      const double m3 = e3 - 3 * mu * e2 + 2 * mu * mu * mu;
-      const double m4 = e4 - 4 * mu * e3 + 6 * mu * mu * e2 - 3 * mu * mu * mu * mu;
-      res[1] = mu;
-      res[2] = var;
-      if (var > 0) {
-        res[3] = m3 / std::pow(var, 1.5);
-        res[4] = m4 / (var * var) - 3.0;
-      }
+    moments_from_sums(sm, out5);
+    return {};
+  };
+  return finish(c, run());
+}
+
+wf_status wf_field_moments_noalloc(wf_ctx* c, const double* v, int32_t masked, double* out5) {
+  if (!c || !v || !out5) return c ? finish(c, fail(WF_EINVAL, "null argument")) : WF_EINVAL;
+  Status s = need(c->have_grid && (!masked || c->have_mask), "needs the grid (and mask)");
+  if (!s.ok()) return finish(c, s);
+  auto run = [&]() -> Status {
+    WF_TRY(set_device(c));
+    // a host pointer reaching the kernel would fault the GPU: refuse it here
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, v) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(WF_EINVAL, "v must be device memory on the context's GPU");
     }
-    for (int k = 0; k < 5; ++k) out5[k] = res[k];
+    if ((at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) ||
+        at.device != c->al.device)
+      return fail(WF_EINVAL, "v must be device memory on the context's GPU");
+    double sm[5];
+    WF_TRY(field_sums_noalloc(v, masked ? c->od.w64.as<double>() : nullptr, c->od.g.m,
+                              c->al.device, sm, c->stream));
+    moments_from_sums(sm, out5);
     return {};
   };
   return finish(c, run());

@@ -198,6 +198,12 @@ Status filter_passes(const OperatorData& od, const double* hrows, const double* 
                      cplx<double>* spec, double* out, hipStream_t s);
 Status field_sums(const double* v, const double* w, int64_t m, DevBuf& parts, const Allocator& al,
                   double out[5], hipStream_t s);
+// field_sums with its partials in a static device array (no allocation);
+// `device` must be the current device
+Status field_sums_noalloc(const double* v, const double* w, int64_t m, int device, double out[5],
+                          hipStream_t s);
+// count, mean, variance, skewness, excess kurtosis from the sums of 1, v .. v^4
+void moments_from_sums(const double sm[5], double out5[5]);
 Status compare_sums(const double* rec, const double* tru, const double* w, int64_t m, DevBuf& parts,
                     DevBuf& flag, const Allocator& al, double out[6], bool* kl_ok, hipStream_t s);
 hipError_t launch_deposit_iw(int scheme, const double* xyz, int64_t ngal, double c, int nd,

@@ -3,6 +3,7 @@
 // eq:DEC, Gaussian smoothing), the inverse-weighting comparator and the
 // quality measures of Sec. 4.1.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -177,6 +178,84 @@ Status field_sums(const double* v, const double* w, int64_t m, DevBuf& parts, co
   for (int b = 0; b < nb; ++b)
     for (int k = 0; k < 5; ++k) out[k] += h[(size_t)b * 5 + k];
   return {};
+}
+
+// ---- allocation-free moments ---------------------------------------------
+// Scratch of field_sums_noalloc: the block partials of k_moments (at most
+// RED_BLOCKS x 5 doubles) and the 5 sums.  A file-scope device array: one copy
+// per GPU, held until the process ends.  Its host-side name is not a device
+// address; host code uses the address hipGetSymbolAddress returns for the
+// current device.  Every call on a GPU uses that GPU's copy: calls that
+// overlap on one GPU race.  Nothing in it needs clearing: k_moments writes
+// every partial it uses and k_sum_parts every sum.
+constexpr int NOALLOC_PARTS = RED_BLOCKS * 5;
+constexpr int NOALLOC_DOUBLES = NOALLOC_PARTS + 8;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_addr[MAX_DEVICES] = {};   // device address of `scratch` per GPU
+
+// The device address of `scratch` on `device`, which must be current: taken
+// once per device and kept.
+Status scratch_of(int device, double** out) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(WF_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_addr[device]) {
+    void* p = nullptr;
+    WF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(WF_EDEVICE, "hipGetSymbolAddress returned a null address");
+    scratch_addr[device] = static_cast<double*>(p);
+  }
+  *out = scratch_addr[device];
+  return {};
+}
+}  // namespace
+
+// out[k] = sum over blocks b of parts[b * ncomp + k], in block order (the
+// order the host uses in field_sums, so both give the same bits)
+__global__ void k_sum_parts(const double* __restrict__ parts, int nb, int ncomp, double* out) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < ncomp) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += parts[(int64_t)b * ncomp + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+Status field_sums_noalloc(const double* v, const double* w, int64_t m, int device, double out[5],
+                          hipStream_t s) {
+  const int nb = red_blocks(m);
+  if ((int64_t)nb * 5 > NOALLOC_PARTS)
+    return fail(WF_EINVAL, "reduction needs more partials than the static scratch holds");
+  double* sc = nullptr;
+  WF_TRY(scratch_of(device, &sc));
+  hipLaunchKernelGGL(k_moments, dim3(nb), dim3(RED_THREADS), 0, s, v, w, m, sc);
+  WF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, sc, nb, 5, sc + NOALLOC_PARTS);
+  WF_HIP(hipGetLastError());
+  WF_HIP(hipMemcpyAsync(out, sc + NOALLOC_PARTS, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+  WF_HIP(hipStreamSynchronize(s));
+  return {};
+}
+
+void moments_from_sums(const double sm[5], double out5[5]) {
+  const double n = sm[0];
+  double res[5] = {n, NAN, NAN, NAN, NAN};
+  if (n > 0) {
+    const double mu = sm[1] / n;
+    const double e2 = sm[2] / n, e3 = sm[3] / n, e4 = sm[4] / n;
+    const double var = e2 - mu * mu;
+    const double m3 = e3 - 3 * mu * e2 + 2 * mu * mu * mu;
+    const double m4 = e4 - 4 * mu * e3 + 6 * mu * mu * e2 - 3 * mu * mu * mu * mu;
+    res[1] = mu;
+    res[2] = var;
+    if (var > 0) {
+      res[3] = m3 / std::pow(var, 1.5);
+      res[4] = m4 / (var * var) - 3.0;
+    }
+  }
+  for (int k = 0; k < 5; ++k) out5[k] = res[k];
 }
 
 Status compare_sums(const double* rec, const double* tru, const double* w, int64_t m, DevBuf& parts,
