@@ -32,13 +32,13 @@ FLOOR = 1e-13
 # (workload, form, k) -> relative L2 spread of the k-th iterate
 SPREADS = {
     ("pl32", "plain", 50): 3.2e-5,
-    ("pl32", "plain", 300): 1.5e-6,
-    ("bbks48", "plain", 50): 2.9e-9,
-    ("bbks48", "plain", 300): 7.6e-13,
-    ("bbks48", "split", 1): 4.1e-15,
-    ("bbks48", "split", 20): 1.4e-9,
-    ("bbks48", "split", 80): 1.7e-8,
-    ("bbks48", "split", 200): 3.1e-14,
+    ("pl32", "plain", 300): 1.9e-6,
+    ("bbks48", "plain", 50): 3.4e-9,
+    ("bbks48", "plain", 300): 7.8e-13,
+    ("bbks48", "split", 1): 3.9e-15,
+    ("bbks48", "split", 20): 9.2e-10,
+    ("bbks48", "split", 80): 2.3e-8,
+    ("bbks48", "split", 200): 3.4e-14,
 }
 
 
