@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define WF_ABI_VERSION 2
+#define WF_ABI_VERSION 3
 
 typedef enum {
   WF_OK = 0,
@@ -117,7 +117,18 @@ typedef struct wf_server wf_server;
  *   check_every host convergence checks every this many iterations (0: 16).
  *               Results do not depend on it: the device stops iterating at
  *               convergence by itself.
- *   precond     wf_precond. */
+ *   precond     wf_precond.
+ *   err_tol     MIXED only (0: the default 5e-7; < 0: no such condition):
+ *               once the FP64 residual meets tol the
+ *               solve goes on for at least one more reliable update, and stops
+ *               at the first update that meets tol again and changed the
+ *               solution s by at most err_tol relative (||s_new - s_old|| /
+ *               ||s_new||, on s = C y for the prior-split form).  The residual
+ *               alone does not bound the error of a mixed solve: FP32 rounding
+ *               of the operator, which grows with nbar, leaves large-scale
+ *               error in the unobserved region that the residual barely
+ *               weights until it has dropped further; that error shows in the
+ *               change the following FP64 refresh makes. */
 typedef struct {
   wf_precision precision;
   double tol;
@@ -126,6 +137,7 @@ typedef struct {
   int32_t max_outer;
   int32_t check_every;
   int32_t precond;
+  double err_tol;
 } wf_solve_opts;
 
 typedef struct {
@@ -137,6 +149,11 @@ typedef struct {
   double model_bytes;         /* algorithmic HBM bytes moved by the solve     */
   double nbar;                /* mean density per cell used                   */
   int32_t status;             /* wf_status of the solve                       */
+  double last_change;         /* MIXED: relative change of s made by the last
+                                 reliable update (see err_tol): with err_tol,
+                                 an estimate of the error left; 0 for FP64    */
+  double latency_ms;          /* server: submit -> result ready on the host;
+                                 0 elsewhere                                  */
 } wf_solve_info;
 
 /* ---- library ----------------------------------------------------------- */
@@ -397,13 +414,22 @@ typedef struct {
   double solves_per_s;      /* completed / (last completion - first arrival) */
   double p50_ms, p99_ms;    /* submit -> result ready on the host            */
   size_t peak_bytes;        /* peak device bytes held by admitted requests   */
+  int64_t cohorts;          /* batched solves started (see wf_server_create) */
+  int32_t largest_cohort;   /* most requests in one batched solve            */
 } wf_server_stats;
 
-/* A continuous-batching server on one device.  Requests are admitted while
- * the sum of their footprints stays within hbm_budget bytes and at most
- * max_active run; admitted requests keep their Krylov state on the device and
- * advance together (requests of equal n share batched launches).
- * wf_server_submit returns WF_ENOMEM if the request can never fit. */
+/* A continuous-batching server on one device.  Requests are admitted in
+ * arrival order while their device memory fits in hbm_budget bytes and fewer
+ * than max_active batched solves run: the request at the head of the queue is
+ * admitted together with every queued request of equal grid, supersampling,
+ * precision and preconditioning (up to 16, as many as fit; masks, priors,
+ * boxes and catalogues may all differ) as one batched solve, whose every pass
+ * is one launch for all of them.  Batched solves run concurrently on their
+ * own streams (max_active of them); Krylov state stays on the device; a request's result
+ * is copied out as soon as its own solve stops, and its gridding buffers are
+ * returned as soon as its data vector is built.  A result is bitwise the same
+ * whatever it was batched with.  wf_server_submit returns WF_ENOMEM if the
+ * request can never fit. */
 wf_status wf_server_create(wf_server** out, int device, size_t hbm_budget,
                            int32_t max_active, wf_alloc_fn alloc,
                            wf_free_fn free_fn, void* user);

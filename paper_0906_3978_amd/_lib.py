@@ -31,14 +31,14 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 class SolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("err_tol", C.c_double)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters_total", C.c_int32), ("outer_steps", C.c_int32),
                 ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double),
                 ("time_ms", C.c_double), ("model_bytes", C.c_double), ("nbar", C.c_double),
-                ("status", C.c_int32)]
+                ("status", C.c_int32), ("last_change", C.c_double), ("latency_ms", C.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -72,7 +72,8 @@ class Profile(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("solves_per_s", C.c_double),
-                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("peak_bytes", C.c_size_t)]
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("peak_bytes", C.c_size_t),
+                ("cohorts", C.c_int64), ("largest_cohort", C.c_int32)]
 
 
 class WienerError(RuntimeError):
@@ -231,6 +232,8 @@ class Info:
     model_bytes: float
     nbar: float
     status: int
+    last_change: float
+    latency_ms: float
     status_name: str
 
 
@@ -239,9 +242,9 @@ def _info(si):
 
 
 def opts(precision="fp64", tol=1e-10, max_iter=10000, inner_tol=0.0, max_outer=0, check_every=0,
-         precond="none"):
+         precond="none", err_tol=0.0):
     return SolveOpts(PRECISIONS[precision], tol, max_iter, inner_tol, max_outer, check_every,
-                     PRECONDS[precond])
+                     PRECONDS[precond], err_tol)
 
 
 class Context:

@@ -55,7 +55,17 @@ struct CgState {
   int32_t pending;   // 1: x still lacks alpha p of the last iteration (applied by the next
                      // z pass, a reliable-update fold or a flush)
   double onorm;      // prior-split solves: ||b|| of the original system (bnorm is ||C b||)
+  // reliable updates: relative change of the solution s made by the last fold,
+  // ||s_new - s_old|| / ||s_new|| (prior-split: measured on s = C y), and the
+  // bound it must meet, besides the residual tolerance, to stop (0: none)
+  double move;
+  double err_tol;
+  int32_t hold;      // 1: residual tolerance met, waiting for the change to fall below err_tol
+  int32_t pad_;
 };
+
+// The prior-split factor table is stored in blocks of this many consecutive kz.
+constexpr int SPLIT_FB = 16;
 
 enum : int32_t {
   CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_BREAKDOWN = 3, CG_STOPPED = 4,

@@ -135,7 +135,55 @@ Status build_xlam(OperatorData& od, hipStream_t s) {
 }
 
 SolveWork::~SolveWork() {
-  if (st_host) (void)hipHostFree(st_host);
+  if (st_host && !view) (void)hipHostFree(st_host);
+}
+
+static void alias_part(DevBuf& dst, const DevBuf& src, size_t per, int slot) {
+  if (src.p) dst.alias(static_cast<char*>(src.p) + per * slot, per);
+  else dst.release();
+}
+
+void SolveWork::make_view(const SolveWork& src, const Grid& g, int slot) {
+  view = true;
+  nrhs = 1;
+  split = src.split;
+  vlen = src.vlen;
+  const size_t m = (size_t)g.m, v = (size_t)vlen, sp = (size_t)g.spec_total;
+  alias_part(b64, src.b64, m * 8, slot);
+  alias_part(x64, src.x64, v * 8, slot);
+  alias_part(r64, src.r64, v * 8, slot);
+  alias_part(p64, src.p64, v * 8, slot);
+  alias_part(q64, src.q64, v * 8, slot);
+  alias_part(spec64, src.spec64, sp * 16, slot);
+  alias_part(x32, src.x32, v * 4, slot);
+  alias_part(r32, src.r32, v * 4, slot);
+  alias_part(p32, src.p32, v * 4, slot);
+  alias_part(q32, src.q32, v * 4, slot);
+  alias_part(spec32, src.spec32, sp * 8, slot);
+  alias_part(bh64, src.bh64, v * 8, slot);
+  alias_part(u64, src.u64, m * 8, slot);
+  alias_part(state, src.state, sizeof(CgState), slot);
+  partials.alias(src.partials.p, src.partials.bytes);
+  st_host = src.st_host + slot;
+  st_cap = 1;
+}
+
+void OperatorData::make_view(const OperatorData& src, int slot, double box) {
+  g = src.g;
+  g.box = box;
+  alias_part(w64, src.w64, (size_t)src.rhs_w * 8, slot);
+  alias_part(w32, src.w32, (size_t)src.rhs_w * 4, slot);
+  tw64.alias(src.tw64.p, src.tw64.bytes);
+  tw32.alias(src.tw32.p, src.tw32.bytes);
+  alias_part(lam64, src.lam64, (size_t)src.rhs_lam * 8, slot);
+  alias_part(xlam64, src.xlam64, (size_t)src.rhs_xlam * 8, slot);
+  alias_part(xlam32, src.xlam32, (size_t)src.rhs_xlam * 4, slot);
+  alias_part(fac64, src.fac64, (size_t)src.rhs_fac * 8, slot);
+  alias_part(fac32, src.fac32, (size_t)src.rhs_fac * 4, slot);
+  fac_ready = src.fac_ready;
+  sd = false;
+  prof = src.prof;
+  rhs_w = rhs_lam = rhs_xlam = rhs_fac = 0;
 }
 
 Status SolveWork::ensure(const Allocator& al, const Grid& g, int nr, bool fp64_cg, bool mixed,
@@ -311,7 +359,7 @@ template <typename T, typename Args> static void set_noise_diag(const OperatorDa
     a.w_scaled = 1;
   } else {
     a.w = w_of<T>(od);
-    a.rhs_w = 0;
+    a.rhs_w = od.rhs_w;
     a.w_scaled = 0;
   }
 }
@@ -328,6 +376,7 @@ static StrArgs<T> str_args(const OperatorData& od, cplx<T>* spec, bool xpass, co
   a.nblk0 = a.s0.n_outer * a.s0.n_btiles;
   a.nblk1 = a.s1.n_outer * a.s1.n_btiles;
   a.lam = lam_of<T>(od);
+  a.rhs_lam = od.rhs_xlam;
   a.tw = tw_of<T>(od);
   a.st = skip != SKIP_NONE ? st : nullptr;
   a.skip = skip;
@@ -471,6 +520,7 @@ static StrArgs<T> split_x_args(const OperatorData& od, const cplx<T>* in, cplx<T
   a.st = skip != SKIP_NONE ? st : nullptr;
   a.skip = skip;
   a.fac = fac_of<T>(od);
+  a.rhs_fac = od.rhs_fac;
   a.in_scale = 1.0 / (double)g.m;
   a.partials = partials;
   return a;

@@ -441,7 +441,7 @@ __device__ __forceinline__ int64_t vec_off(int outer, int ncols, int c, int i) {
 // blocks of FB consecutive kz: [|my|][kz / FB][|mx|][kz % FB].  An x-pass
 // tile (one |my|, up to FB consecutive kz, every x) then reads one
 // contiguous block, and kz pairs load as one aligned vector.
-constexpr int FB = 16;
+constexpr int FB = SPLIT_FB;
 template <int N> constexpr int split_kzb() { return (N / 2 + FB) / FB; }  // kz blocks
 template <int N>
 __device__ __forceinline__ int64_t fac_off(int my, int mx, int kz) {
@@ -529,6 +529,8 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   __shared__ double red[REDUCE ? NT / 64 : 1];
   const int rhs = blockIdx.y;
   if (a.st && skip_rhs(a.st + rhs, a.skip)) return;
+  const T* fac_r = a.fac + rhs * a.rhs_fac;
+  const T* lam_r = a.lam + rhs * a.rhs_lam;
   int blk = blockIdx.x;
   const bool second = blk >= a.nblk0;
   const Seg<T> s = second ? a.s1 : a.s0;
@@ -586,7 +588,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
             T f[CW];
             int kz[CW];
             bool dc[CW];
-            split_facs<T, N, CW>(a.fac, s, outer, b0 + b, i, f, kz, dc);
+            split_facs<T, N, CW>(fac_r, s, outer, b0 + b, i, f, kz, dc);
 #pragma unroll
             for (int j = 0; j < CW; ++j) {
               const T g = f[j] * ((T)a.in_scale / sqrt_d<T, N>(kz[j]));
@@ -621,7 +623,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           T f;
           int kz;
           bool dc;
-          split_facs<T, N, 1>(a.fac, s, outer, b0 + b, i, &f, &kz, &dc);
+          split_facs<T, N, 1>(fac_r, s, outer, b0 + b, i, &f, &kz, &dc);
           f *= (T)a.in_scale / sqrt_d<T, N>(kz);
           v = {v.x * f, v.y * f};
         }
@@ -698,7 +700,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
         const int b = bf % TB, j = bf / TB, cb = b0 + b;
         const int my = s.lam_y_outer ? my_o : signed_m(cb, N);
         const int kz = s.lam_kz < 0 ? cb : s.lam_kz;
-        const T* row = a.lam + (int64_t)((my < 0 ? -my : my) * HN + kz) * ROW;
+        const T* row = lam_r + (int64_t)((my < 0 ? -my : my) * HN + kz) * ROW;
         const T* lo = row + j * HR;
         const T* hi = row + (L - j) * HR;
         if constexpr ((HR * sizeof(T)) % 16 == 0) {
@@ -757,7 +759,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           T f[CW];
           int kz[CW];
           bool dc[CW];
-          split_facs<T, N, CW>(a.fac, s, outer, b0 + b, i, f, kz, dc);
+          split_facs<T, N, CW>(fac_r, s, outer, b0 + b, i, f, kz, dc);
           R o;
 #pragma unroll
           for (int j = 0; j < CW; ++j) {
@@ -778,7 +780,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
         T f;
         int kz;
         bool dc;
-        split_facs<T, N, 1>(a.fac, s, outer, b0 + b, i, &f, &kz, &dc);
+        split_facs<T, N, 1>(fac_r, s, outer, b0 + b, i, &f, &kz, &dc);
         const V pv = REDUCE ? s.aux[off] : V{T(0), T(0)};
         cplx<double> bv{0.0, 0.0};
         if constexpr (MODE == SM_FWD_RES) bv = s.bvec[off];
@@ -866,7 +868,9 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partials, int np
     if (st->reliable) {
       // the recursive residual decides when to refresh it in FP64; only the
       // FP64 residual decides convergence
-      if (sqrt(rho_new) <= st->delta * st->rmax || rel <= st->tol || st->iter >= st->max_iter) {
+      // (while holding for the solution to settle only the drop by delta triggers)
+      if (sqrt(rho_new) <= st->delta * st->rmax || (rel <= st->tol && !st->hold) ||
+          st->iter >= st->max_iter) {
         st->done = 1;
         st->status = CG_UPDATE;
       }

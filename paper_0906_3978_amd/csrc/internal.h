@@ -54,6 +54,12 @@ struct DevBuf {
   ~DevBuf() { release(); }
   void release();
   Status ensure(const Allocator& al, size_t b);  // keeps contents only if big enough already
+  // non-owning alias of memory owned elsewhere (never freed through this buffer)
+  void alias(void* ptr, size_t b) {
+    release();
+    p = ptr;
+    bytes = b;
+  }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
@@ -117,7 +123,13 @@ struct OperatorData {
   // dg (nbar w g per RHS, n^3 apart) instead of nbar w
   bool sd = false;
   DevBuf dg64, dg32;
+  // per-RHS tables (several solves of one grid with their own masks and
+  // priors): element strides between the RHS's copies, 0 when shared
+  int64_t rhs_w = 0, rhs_lam = 0, rhs_xlam = 0, rhs_fac = 0;
   Profiler* prof = nullptr;   // optional
+  // a one-RHS view of RHS `slot` of `src` (tables of that RHS, shared
+  // twiddles, box `box`); the view owns nothing
+  void make_view(const OperatorData& src, int slot, double box);
 };
 
 // Workspace of solves on a grid for `nrhs` right-hand sides.
@@ -134,7 +146,12 @@ struct SolveWork {
   DevBuf state, partials;
   CgState* st_host = nullptr;   // pinned mirror of the state array
   int st_cap = 0;
+  bool view = false;            // a view of one RHS of another SolveWork (owns nothing)
   ~SolveWork();
+  // one-RHS view of RHS `slot` of src (its vectors, state and mirror; the
+  // partials of src are shared, so the view's launches must not overlap
+  // src's)
+  void make_view(const SolveWork& src, const Grid& g, int slot);
   // b, x, r and the FP64 spectrum always; p, q (FP64 CG); the FP32 set (mixed)
   Status ensure(const Allocator& al, const Grid& g, int nrhs, bool fp64_cg, bool mixed,
                 bool split = false);

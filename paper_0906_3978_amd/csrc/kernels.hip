@@ -277,25 +277,79 @@ hipError_t launch_rel_init(double* x64, double* r64, const double* b, float* x32
   return hipGetLastError();
 }
 
+// Weight of element i (a double of an interleaved half spectrum: main
+// [x][y][kz < n/2] then the kz = n/2 plane [x][y]) in ||C v||^2: the square
+// of the prior-split factor of its mode.
+__device__ __forceinline__ double split_weight(const double* fac, int n, int64_t spec_main,
+                                              int64_t i) {
+  const int64_t ci = i >> 1;
+  const int h = n / 2;
+  int x, y, kz;
+  if (ci < spec_main) {
+    kz = (int)(ci % h);
+    const int64_t row = ci / h;
+    y = (int)(row % n);
+    x = (int)(row / n);
+  } else {
+    const int64_t cj = ci - spec_main;
+    kz = h;
+    y = (int)(cj % n);
+    x = (int)(cj / n);
+  }
+  const int mx = x <= h ? x : n - x, my = y <= h ? y : n - y;
+  const int kzb = (h + SPLIT_FB) / SPLIT_FB;
+  const double c = fac[((int64_t)(my * kzb + kz / SPLIT_FB) * (h + 1) + mx) * SPLIT_FB +
+                       kz % SPLIT_FB];
+  return c * c;
+}
+
+// RHS waiting for an update: x64 += x32 (+ the pending alpha p32), x32 = 0,
+// and move = ||fold|| / ||x64 new||, weighted by the prior-split factor
+// squared when `fac` is given (then the vectors are half spectra of y and the
+// norms are those of s = C y).
 __global__ __launch_bounds__(VEC_THREADS) void k_rel_fold(double* x64, float* x32, const float* p32,
-                                                          int64_t m, int64_t rs,
-                                                          const CgState* st_all) {
+                                                          int64_t m, int64_t rs, double* partials,
+                                                          const double* fac, int n,
+                                                          int64_t spec_main, int64_t fac_rs,
+                                                          CgState* st_all) {
+  __shared__ double red[VEC_THREADS / 64];
+  __shared__ int last_flag;
   const int rhs = blockIdx.y;
-  const CgState* st = st_all + rhs;
+  CgState* st = st_all + rhs;
   if (st->status != CG_UPDATE) return;
   const float alpha = st->pending ? (float)st->alpha : 0.f;
   const int64_t o = rhs * rs;
+  const double* fr = fac ? fac + rhs * fac_rs : nullptr;
+  double dd = 0.0, xx = 0.0;
   const int64_t stride = (int64_t)gridDim.x * VEC_THREADS;
   for (int64_t i = (int64_t)blockIdx.x * VEC_THREADS + threadIdx.x; i < m; i += stride) {
-    x64[o + i] += (double)(x32[o + i] + alpha * p32[o + i]);
+    const double d = (double)(x32[o + i] + alpha * p32[o + i]);
+    const double xn = x64[o + i] + d;
+    x64[o + i] = xn;
     x32[o + i] = 0.f;
+    const double wgt = fr ? split_weight(fr, n, spec_main, i) : 1.0;
+    dd += wgt * d * d;
+    xx += wgt * xn * xn;
+  }
+  const double pd = block_sum(dd, red);
+  const double px = block_sum(xx, red);
+  double* parts = partials + (int64_t)rhs * 2 * gridDim.x;
+  if (publish_partial2(pd, px, parts, &st->ticket, gridDim.x, &last_flag)) {
+    const double td = reduce_partials_strided(parts, gridDim.x, 2, red);
+    const double tx = reduce_partials_strided(parts + 1, gridDim.x, 2, red);
+    if (threadIdx.x == 0) {
+      st->move = tx > 0.0 ? sqrt(td / tx) : 0.0;
+      reset_ticket(&st->ticket);
+    }
   }
 }
 
 hipError_t launch_rel_fold(double* x64, float* x32, const float* p32, int64_t m, int64_t rs,
-                           const CgState* st, int nrhs, hipStream_t s) {
+                           double* partials, const double* fac, int n, int64_t spec_main,
+                           int64_t fac_rs, CgState* st, int nrhs, hipStream_t s) {
   dim3 grid(vec_blocks(m), nrhs);
-  hipLaunchKernelGGL(k_rel_fold, grid, dim3(VEC_THREADS), 0, s, x64, x32, p32, m, rs, st);
+  hipLaunchKernelGGL(k_rel_fold, grid, dim3(VEC_THREADS), 0, s, x64, x32, p32, m, rs, partials,
+                     fac, n, spec_main, fac_rs, st);
   return hipGetLastError();
 }
 
@@ -323,14 +377,21 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const dou
       st->updates += 1;
       st->pending = 0;  // folded
       const double rel = sqrt(st->outer_rr) / st->bnorm;
-      if (rel <= st->tol) {
+      // with err_tol, the residual must already have met tol at the previous
+      // update (hold) and this update's change of the solution, which shows
+      // error the residual had hidden, must be at most err_tol
+      const bool settled = !(st->err_tol > 0.0) || (st->hold && st->move <= st->err_tol);
+      if (rel <= st->tol && settled) {
         st->status = CG_CONVERGED;
       } else if (st->iter >= st->max_iter) {
         st->status = CG_MAXITER;
       } else if (st->max_updates > 0 && st->updates >= st->max_updates) {
         st->status = CG_STOPPED;
       } else {
-        // continue from the refreshed residual with the same direction
+        // continue from the refreshed residual with the same direction; with
+        // the residual met but the solution still moving, the next update
+        // comes when the residual has dropped by delta again
+        st->hold = rel <= st->tol ? 1 : 0;
         st->beta = tot / st->rho_old;
         st->rho = tot;
         st->rmax = sqrt(tot);
@@ -353,7 +414,7 @@ hipError_t launch_rel_reset(float* r32, const double* r64, int64_t m, int64_t rs
 // Initialises the scalar state of a solve whose nbar was written to the device
 // by the data-vector kernel (used by the server, which never waits on it).
 __global__ void k_state_init(CgState* st_all, const double* nbar, double tol, int32_t max_iter,
-                             double delta, int32_t max_updates) {
+                             double delta, int32_t max_updates, double err_tol) {
   if (threadIdx.x != 0) return;
   CgState* st = st_all + blockIdx.x;
   CgState z{};
@@ -362,13 +423,29 @@ __global__ void k_state_init(CgState* st_all, const double* nbar, double tol, in
   z.max_iter = max_iter;
   z.delta = delta;
   z.max_updates = max_updates;
+  z.err_tol = err_tol;
   *st = z;
 }
 
 hipError_t launch_state_init(CgState* st, const double* nbar, double tol, int32_t max_iter,
-                             double delta, int32_t max_updates, int nrhs, hipStream_t s) {
+                             double delta, int32_t max_updates, double err_tol, int nrhs,
+                             hipStream_t s) {
   hipLaunchKernelGGL(k_state_init, dim3(nrhs), dim3(64), 0, s, st, nbar, tol, max_iter, delta,
-                     max_updates);
+                     max_updates, err_tol);
+  return hipGetLastError();
+}
+
+// Stops one solve where it stands (a cancelled request): kernels skip it from
+// then on.
+__global__ void k_state_stop(CgState* st) {
+  if (threadIdx.x == 0) {
+    st->done = 1;
+    st->status = CG_STOPPED;
+  }
+}
+
+hipError_t launch_state_stop(CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_stop, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 

@@ -103,6 +103,7 @@ template <typename T> struct StrArgs {
                             // [|my|][kz / 16][|mx|][kz % 16]
   double in_scale;          // SM_INV_SCALE: 1 / M
   double* partials;         // SM_FWD_CGQ / SM_FWD_RES: per RHS, one per block
+  int64_t rhs_lam, rhs_fac; // per-RHS strides of lam and fac (0: shared)
 };
 
 int strided_tb(int n, bool fp64);   // batch width of a strided tile
@@ -148,9 +149,15 @@ template <typename T> hipError_t launch_cg_flush(T* x, const T* p, int64_t m, in
 hipError_t launch_rel_init(double* x64, double* r64, const double* b, float* x32, float* r32,
                            int64_t m, int64_t rhs_stride, double* partials, CgState* st, int nrhs,
                            hipStream_t s);
-// RHS waiting for an update: x64 += x32 (+ the pending alpha p32), x32 = 0
+// RHS waiting for an update: x64 += x32 (+ the pending alpha p32), x32 = 0,
+// and the relative change of the solution into the state (`move`); with `fac`
+// (the FP64 prior-split factor table of an n^3 grid, per-RHS stride fac_rs)
+// the vectors are half spectra (spec_main complex in the main part) and the
+// change is measured on s = C y
 hipError_t launch_rel_fold(double* x64, float* x32, const float* p32, int64_t m,
-                           int64_t rhs_stride, const CgState* st, int nrhs, hipStream_t s);
+                           int64_t rhs_stride, double* partials, const double* fac, int n,
+                           int64_t spec_main, int64_t fac_rs, CgState* st, int nrhs,
+                           hipStream_t s);
 // RHS waiting for an update (after r64 = b - A64 x64): r32 = (float) r64, rho,
 // convergence test on the FP64 residual, resume or stop
 hipError_t launch_rel_reset(float* r32, const double* r64, int64_t m, int64_t rhs_stride,
@@ -158,7 +165,11 @@ hipError_t launch_rel_reset(float* r32, const double* r64, int64_t m, int64_t rh
 
 // state of nrhs solves from device-resident nbar values
 hipError_t launch_state_init(CgState* st, const double* nbar, double tol, int32_t max_iter,
-                             double delta, int32_t max_updates, int nrhs, hipStream_t s);
+                             double delta, int32_t max_updates, double err_tol, int nrhs,
+                             hipStream_t s);
+
+// marks one solve stopped (done, CG_STOPPED)
+hipError_t launch_state_stop(CgState* st, hipStream_t s);
 
 hipError_t launch_fill_i64(long long* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_c64(double2* p, int64_t n, hipStream_t s);

@@ -7,6 +7,10 @@
 namespace wf {
 
 Status validate_opts(const wf_solve_opts& o);
+// The solution-change bound of a mixed solve (wf_solve_opts.err_tol: 0 gives
+// this default, a negative value none); 0 (none) for FP64 solves.
+constexpr double DEFAULT_ERR_TOL = 5e-7;
+double effective_err_tol(const wf_solve_opts& o);
 
 struct SolveRequest {
   const OperatorData* od = nullptr;

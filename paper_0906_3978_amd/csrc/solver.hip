@@ -29,7 +29,13 @@ Status validate_opts(const wf_solve_opts& o) {
   if (o.max_outer < 0 || o.check_every < 0) return fail(WF_EINVAL, "max_outer and check_every must be >= 0");
   if (o.precond != WF_PRECOND_NONE && o.precond != WF_PRECOND_PRIOR)
     return fail(WF_EINVAL, "unknown precond");
+  if (!std::isfinite(o.err_tol)) return fail(WF_EINVAL, "err_tol must be finite");
   return {};
+}
+
+double effective_err_tol(const wf_solve_opts& o) {
+  if (o.precision != WF_MIXED || o.err_tol < 0.0) return 0.0;
+  return o.err_tol > 0.0 ? o.err_tol : DEFAULT_ERR_TOL;
 }
 
 int severity(wf_status s) {
@@ -220,8 +226,9 @@ Status solve_update(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s
   CgState* st = sw.state.as<CgState>();
   double* parts = sw.partials.as<double>();
   const int64_t vl = sw.split ? sw.vlen : g.m;
-  WF_HIP(launch_rel_fold(sw.x64.as<double>(), sw.x32.as<float>(), sw.p32.as<float>(), vl, vl, st,
-                         nr, s));
+  WF_HIP(launch_rel_fold(sw.x64.as<double>(), sw.x32.as<float>(), sw.p32.as<float>(), vl, vl, parts,
+                         sw.split ? od.fac64.as<double>() : nullptr, g.n, g.spec_main,
+                         od.rhs_fac, st, nr, s));
   if (sw.split) {
     WF_TRY(split_passes<double>(od, SM_FWD_RES, sw.x64.as<double>(), sw.spec64.as<double2>(),
                                 sw.r64.as<double>(), sw.bh64.as<double>(), st, parts, nr,
@@ -277,6 +284,7 @@ void solve_infos(const CgState* st, int nr, bool mixed, bool split, const Grid& 
     in.model_bytes = mb * M;
     in.nbar = c.nbar;
     in.status = map_cg_status(c.status);
+    in.last_change = mixed ? c.move : 0.0;
   }
 }
 
@@ -299,6 +307,7 @@ Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
     st[i].max_iter = o.max_iter;
     st[i].delta = o.inner_tol > 0 ? o.inner_tol : 0.1;
     st[i].max_updates = o.max_outer;
+    st[i].err_tol = effective_err_tol(o);
   }
   WF_TRY(push_states(sw, st, s));
   Timer tm;

@@ -3,13 +3,17 @@
 Two implementations of the same operator round differently, so their k-th
 CG iterates differ by an amount that depends on the problem and on k, not on
 either implementation being wrong.  This module measures that amount on the
-oracle alone: every operator application is multiplied element by element by
-(1 + EPS xi), xi standard normal from a seeded generator, and the right-hand
-side by (1 + EPS_B xi'), and the perturbed k-th iterate is compared with the
-unperturbed one.  EPS = 1e-15 bounds the relative rounding of an FP64 3D FFT
-of these sizes (about sqrt(log2 M) 1.1e-16 = 5e-16 at 48^3); EPS_B = 1e-14 is
-the agreement of the gridded data with the oracle's (the n^o parity bound is
-1e-13 of its maximum, measured 2.5e-14).
+oracle alone, with every operator application rounded like an FFT pipeline:
+white noise of EPS times the root mean square of each transformed field is
+added to it -- to the forward spectrum before the Fourier diagonal multiplies
+it (so the forward transform's error is scaled by Lambda, or by the split
+factor, as in any implementation) and to the result of each inverse
+transform -- and the right-hand side gets EPS_B times its own.  A 3D FFT's
+rounding is of that form, about sqrt(log2 M) 1.1e-16 of the field's norm
+spread over every element (5e-16 at 256^3), and EPS = 1e-15 bounds it at the
+sizes tested; EPS_B = 1e-14 bounds the agreement of the gridded data with the
+oracle's (the n^o parity bound is 1e-13 of its maximum).  The perturbed k-th
+iterate is compared with the unperturbed one.
 
 SPREADS holds the spreads measured this way (the larger of two seed pairs)
 for the workloads and iteration counts of the fixed-iteration GPU tests;
@@ -32,13 +36,13 @@ FLOOR = 1e-13
 # (workload, form, k) -> relative L2 spread of the k-th iterate
 SPREADS = {
     ("pl32", "plain", 50): 3.2e-5,
-    ("pl32", "plain", 300): 1.9e-6,
-    ("bbks48", "plain", 50): 3.4e-9,
-    ("bbks48", "plain", 300): 7.8e-13,
-    ("bbks48", "split", 1): 3.9e-15,
-    ("bbks48", "split", 20): 9.2e-10,
-    ("bbks48", "split", 80): 2.3e-8,
-    ("bbks48", "split", 200): 3.4e-14,
+    ("pl32", "plain", 300): 5.1e-7,
+    ("bbks48", "plain", 50): 5.7e-10,
+    ("bbks48", "plain", 300): 9.7e-13,
+    ("bbks48", "split", 1): 3.6e-15,
+    ("bbks48", "split", 20): 1.5e-9,
+    ("bbks48", "split", 80): 2.1e-8,
+    ("bbks48", "split", 200): 1.4e-13,
 }
 
 
@@ -47,24 +51,68 @@ def bound(workload, form, k):
     return max(FACTOR * SPREADS[(workload, form, k)], FLOOR)
 
 
+def _rms(a):
+    return math.sqrt(float(np.vdot(a, a).real) / a.size)
+
+
 class PerturbedSystem:
-    """An oracle system whose every application is perturbed by relative
-    noise of size eps (seeded)."""
+    """An oracle plain system (oracle.wiener.System) whose every application
+    rounds like an FFT pipeline: white noise of eps times the root mean square
+    of the forward spectrum is added before the Fourier diagonal multiplies
+    it (so, as in any implementation, the forward transform's error is
+    scaled by Lambda), and of eps times that of the result after the inverse
+    transform (seeded)."""
 
     def __init__(self, base, eps=EPS, seed=0):
         self.base = base
         self.eps = eps
         self.rng = np.random.Generator(np.random.PCG64(seed))
 
+    def _noise(self, a):
+        if np.iscomplexobj(a):
+            z = self.rng.standard_normal(a.shape) + 1j * self.rng.standard_normal(a.shape)
+            return (self.eps * _rms(a) / math.sqrt(2.0)) * z
+        return (self.eps * _rms(a)) * self.rng.standard_normal(a.shape)
+
     def apply(self, v):
-        a = self.base.apply(v)
-        return a * (1.0 + self.eps * self.rng.standard_normal(a.shape))
+        b = self.base
+        vk = b._rfft(v)
+        vk = vk + self._noise(vk)
+        out = b._irfft(b.lam * vk)
+        return out + self._noise(out) + b.nw * v
+
+
+class PerturbedSplit:
+    """The prior-split system (C A C) of an oracle system with the same
+    rounding model: the forward spectra of its real-space stage get noise of
+    eps times their size before the split factor multiplies them, the real
+    field after the inverse transform likewise (seeded)."""
+
+    def __init__(self, sp, eps=EPS, seed=0):
+        self.sp = sp
+        self.pert = PerturbedSystem(sp.base, eps, seed)
+
+    def apply(self, y):
+        sp, pb = self.sp, self.pert
+        b = sp.base
+        u = b._irfft(sp.c * b._rfft(y))              # C y
+        u = u + pb._noise(u)
+        g = b.nw * u                                  # the noise term of A on C y
+        gk = b._rfft(g)
+        gk = gk + pb._noise(gk)
+        out = b._irfft(sp.c * gk)                     # C n w C y
+        out = out + pb._noise(out)
+        # the prior part of C A C is the identity off the monopole
+        yk = b._rfft(y)
+        yk[0, 0, 0] = 0.0
+        return out + b._irfft(yk)
 
 
 def perturbed_rhs(b, seed, eps=EPS_B):
-    """b times (1 + eps xi), xi standard normal (seeded)."""
+    """b plus white noise of eps times its root mean square (seeded)."""
+    b = np.asarray(b, dtype=np.float64)
     rng = np.random.Generator(np.random.PCG64(1000 + seed))
-    return b * (1.0 + eps * rng.standard_normal(np.shape(b)))
+    return b + (eps * _rms(b)) * rng.standard_normal(b.shape)
 
 
 def rel_l2(a, b):
@@ -96,7 +144,7 @@ def split_spreads(system, b, ks, seeds=(1, 2), eps=EPS, eps_b=EPS_B):
     ref = ow.cg(sp, cb, 0.0, ks[-1], keep=ks)
     worst = {k: 0.0 for k in ks}
     for s in seeds:
-        run = ow.cg(PerturbedSystem(sp, eps, s), sp.split(perturbed_rhs(b, s, eps_b)), 0.0,
+        run = ow.cg(PerturbedSplit(sp, eps, s), sp.split(perturbed_rhs(b, s, eps_b)), 0.0,
                     ks[-1], keep=ks)
         for k in ks:
             worst[k] = max(worst[k], rel_l2(sp.split(run["kept"][k]), sp.split(ref["kept"][k])))

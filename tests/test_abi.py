@@ -31,7 +31,7 @@ def test_binding_covers_header():
 
 def test_version_and_status_strings():
     L = wf.lib()
-    assert L.wf_abi_version() == 2
+    assert L.wf_abi_version() == 3
     for code in range(8):
         assert L.wf_status_str(code)
     assert b"unknown" in L.wf_status_str(99)

@@ -99,3 +99,69 @@ def test_invalid_and_cancel(reqs):
         assert done
         assert info.status in (WF_OK, 2)  # finished before the cancel, or cancelled
         srv.fetch(t, reqs[3]["n"], allow=(WF_OK, 2))
+
+
+def test_served_requests_against_oracle():
+    """Requests of the serving recipe at 64^3 and 128^3 (random cap, radial
+    scale and prior amplitude; mixed prior-split CG to the split residual
+    3e-7), served together: each result within 1e-6 relative L2 of the
+    oracle's A^-1 b (its split CG to 1e-12)."""
+    import paper_0906_3978_amd as wf
+    reqs = []
+    for i, n in enumerate([64, 128, 64]):
+        wl = synth.serving_request(i, base_seed=7100, grids=(n,))
+        wl.n_target = min(wl.n_target, 300_000)
+        ptab = wl.ptab()
+        w = wl.mask()
+        reqs.append((wl, ptab, w, wl.catalogue(ptab, w).xyz))
+    kw = dict(precision="mixed", precond="prior", tol=3e-7, max_iter=100000)
+    with wf.Server(0, hbm_budget=4 << 30, max_active=4) as srv:
+        tickets = [srv.submit(wl.n, wl.box, w, p, xyz, "cic", 2, **kw) for wl, p, w, xyz in reqs]
+        got = [srv.wait(t, wl.n) for t, (wl, _, _, _) in zip(tickets, reqs)]
+    for (wl, p, w, xyz), (x, info) in zip(reqs, got):
+        assert info.status == WF_OK
+        res = ow.reconstruct(xyz, wl.n, wl.box, w, p, "cic", 2, 0.0, 0, workers=16)
+        ref = ow.split_cg(res["system"], res["b"], 1e-12, 100000)
+        err = rel_l2(x, ref["x"])
+        print(f"served {wl.n}^3: {len(xyz)} galaxies, {info.iters_total} iterations, "
+              f"error {err:.3e}")
+        assert err < 1e-6
+
+
+def test_queued_requests_of_equal_kind_share_one_batched_solve():
+    """With one batched solve in flight (max_active = 1), requests queued
+    behind a long one are admitted together when it finishes: four 24^3
+    requests with different masks, priors and catalogues form one cohort, and
+    each result equals the same request served alone, bit for bit."""
+    import paper_0906_3978_amd as wf
+    big = synth.serving_request(0, base_seed=9100, box=300.0, grids=(64,))
+    big.n_target = 300_000
+    bp, bw = big.ptab(), big.mask()
+    bxyz = big.catalogue(bp, bw).xyz
+    small = []
+    for i in range(4):
+        wl = synth.serving_request(i + 1, base_seed=9100, box=300.0, grids=(24,))
+        wl.n_target = min(wl.n_target, 30000)
+        p, w = wl.ptab(), wl.mask()
+        small.append((wl, p, w, wl.catalogue(p, w).xyz))
+    kw = dict(precision="mixed", precond="prior", tol=1e-9, max_iter=100000)
+    alone = []
+    with wf.Server(0, hbm_budget=2 << 30, max_active=1) as srv:
+        for wl, p, w, xyz in small:
+            alone.append(srv.wait(srv.submit(wl.n, wl.box, w, p, xyz, "cic", 2, **kw), wl.n))
+        assert srv.stats()["largest_cohort"] == 1
+    with wf.Server(0, hbm_budget=2 << 30, max_active=1) as srv:
+        tb = srv.submit(big.n, big.box, bw, bp, bxyz, "cic", 2, precision="fp64", tol=1e-12,
+                        max_iter=100000)
+        ts = [srv.submit(wl.n, wl.box, w, p, xyz, "cic", 2, **kw) for wl, p, w, xyz in small]
+        xb, ib = srv.wait(tb, big.n)
+        got = [srv.wait(t, wl.n) for t, (wl, _, _, _) in zip(ts, small)]
+        st = srv.stats()
+    print(f"cohorts {st['cohorts']}, largest {st['largest_cohort']}, big solve "
+          f"{ib.iters_total} iterations")
+    assert ib.status == WF_OK
+    assert st["cohorts"] == 2 and st["largest_cohort"] == 4
+    for (xa, ia), (xg, ig) in zip(alone, got):
+        assert ig.status == WF_OK
+        assert ig.iters_total == ia.iters_total
+        assert np.array_equal(xa, xg)
