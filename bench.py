@@ -76,40 +76,143 @@ class _IterationClock(list):
         super().append(time.perf_counter())
 
 
-def cpu_baseline(wl, ptab, w, n_gal, iters_fp64, precond="none"):
-    """The oracle's CG on the same system (plain, or on the prior-split system
-    for precond="prior"), timed on the host cores: the span of its second
-    iteration (one operator application and the vector updates), scaled to a
-    whole FP64 solve of `iters_fp64` iterations (about 30 s of host time at
-    512^3, set-up included)."""
-    from threadpoolctl import threadpool_limits
+def cpu_baseline(wl, ptab, w, xyz, iters_fp64, precond="prior", cg_iters=20):
+    """The oracle timed on the host, phase by phase, on the workload's own
+    catalogue: its integer deposit, its low-pass (scipy's FFT on the host's
+    threads, at most 16), the data vector, and `cg_iters` FP64 CG iterations
+    (prior-split CG for precond="prior": the oracle forms C A C as three FFT
+    pairs per iteration, where the library needs one), whose median
+    iteration time is extrapolated to the `iters_fp64` iterations of an FP64
+    solve of the same system.  Returns the baseline and its per-phase times."""
+    from oracle import deposit as od
+    from oracle import supersample as oss
     from oracle import wiener as ow
-    nbar = ow.mean_density(n_gal, w)
-    rng = np.random.Generator(np.random.PCG64(7))
-    b = np.where(w > 0, rng.standard_normal(w.shape), 0.0)
-    solve = ow.split_cg if precond == "prior" else ow.cg
-    name = "prior-split CG" if precond == "prior" else "plain-CG"
-
-    def one_iteration(system):
-        clock = _IterationClock()
-        solve(system, b, 0.0, 2, record=clock)
-        return clock[1] - clock[0]
-
-    with threadpool_limits(1):
-        dt = one_iteration(ow.System(wl.n, wl.box, w, ptab, nbar))
-    base = {"value": 1.0 / (dt * iters_fp64), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"the second {name} iteration of the FP64 numpy oracle on the "
-                       f"{wl.n}^3 system ({dt:.2f} s, one core) scaled to the "
-                       f"{iters_fp64} iterations of one FP64 solve; gridding not included"),
-            "host": host_cpu()}
-    # CPU best effort: the same algorithm with scipy's FFT on all the host's
-    # cores (at most 16, the share of one GPU)
     workers = min(16, os.cpu_count() or 1)
-    dt_mt = one_iteration(ow.System(wl.n, wl.box, w, ptab, nbar, workers=workers))
-    best = {"value": 1.0 / (dt_mt * iters_fp64), "unit": "solves/s", "cores": workers,
-            "kind": "oracle with scipy.fft workers",
-            "sample": f"the second iteration ({dt_mt:.2f} s) scaled to {iters_fp64}"}
-    return base, best
+    t = time.perf_counter()
+    grid = od.deposit(xyz, wl.supersample * wl.n, wl.box, wl.scheme)
+    t_dep = time.perf_counter() - t
+    t = time.perf_counter()
+    g = grid.astype(np.float64) * od.scheme_unit(wl.scheme)
+    del grid
+    nobs = oss.lowpass_decimate(g, wl.n, workers) if wl.supersample == 2 else g
+    del g
+    t_lp = time.perf_counter() - t
+    t = time.perf_counter()
+    nbar = ow.mean_density(len(xyz), w)
+    b = ow.data_vector(nobs, w, nbar)
+    t_rhs = time.perf_counter() - t
+    system = ow.System(wl.n, wl.box, w, ptab, nbar, workers=workers)
+    solve = ow.split_cg if precond == "prior" else ow.cg
+    clock = _IterationClock()
+    t = time.perf_counter()
+    solve(system, b, 0.0, cg_iters, record=clock)
+    t_cg = time.perf_counter() - t
+    spans = np.diff(np.asarray(clock))
+    per_it = float(np.median(spans))
+    total = t_dep + t_lp + t_rhs + per_it * iters_fp64
+    name = "prior-split CG (three FFT pairs per iteration)" if precond == "prior" else "plain CG"
+    return {"value": 1.0 / total, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": (f"the oracle on the {wl.n}^3 workload: deposit {t_dep:.2f} s, low-pass "
+                       f"{t_lp:.2f} s, data vector {t_rhs:.2f} s, {cg_iters} FP64 {name} "
+                       f"iterations ({t_cg:.1f} s, median {per_it:.3f} s each) extrapolated to "
+                       f"the {iters_fp64} iterations of the FP64 solve"),
+            "phases_s": {"deposit": round(t_dep, 3), "lowpass": round(t_lp, 3),
+                         "data_vector": round(t_rhs, 3), "cg_iteration": round(per_it, 4),
+                         "cg_iterations_timed": cg_iters, "cg_iterations_extrapolated": iters_fp64},
+            "extrapolated": True, "host": host_cpu()}
+
+
+def _iteration_roofline(prof, keys, n):
+    """Per-iteration time, algorithmic bytes and HBM fraction from the live
+    profiler's classes of one CG iteration."""
+    if not all(k in prof and prof[k]["launches"] for k in keys):
+        return None
+    it_ms = sum(prof[k]["ms"] / prof[k]["launches"] for k in keys)
+    it_b = sum(prof[k]["bytes"] / prof[k]["launches"] for k in keys)
+    ach = it_b / (it_ms * 1e-3) / 1e9
+    return {"ms": round(it_ms, 4), "bytes": it_b, "achieved_gbs": round(ach, 1),
+            "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_cell": round(it_b / n ** 3, 2)}
+
+
+PLAIN_F64 = ["zfwd_f64", "yfwd_f64", "xlam_f64", "yinv_f64", "zinv_f64", "update_f64"]
+PLAIN_F32 = ["zfwd_f32", "yfwd_f32", "xlam_f32", "yinv_f32", "zinv_f32", "update_f32"]
+SPLIT_F32 = ["sxinv_f32", "yinv_f32", "szw_f32", "yfwd_f32", "sxfwd_f32", "update_f32"]
+
+
+def _dominant(prof, keys):
+    d = max(keys, key=lambda k: prof[k]["ms"])
+    v = prof[d]
+    avg = v["ms"] * 1e-3 / v["launches"]
+    ach = v["bytes"] / v["launches"] / avg / 1e9
+    return {"kernel": d, "avg_launch_us": round(avg * 1e6, 2), "achieved_gbs": round(ach, 1),
+            "frac": round(ach / HBM_PEAK_GBS, 4)}
+
+
+def fp64_config_run(name, reps=3, cpu_full=False):
+    """A plain FP64 configuration (pl32: 32^3 power law, NGP, residual 1e-10;
+    bbks256: 256^3 BBKS, CIC 2x supersampled, residual 1e-6) on its synthetic
+    catalogue already in HBM: gridding plus the FP64 CG solve, median of
+    `reps`, with the FP64 iteration's roofline; the oracle beside it (full
+    solves, median of 3, when cpu_full, else phases with 20 CG iterations
+    extrapolated)."""
+    import torch
+    import synth
+    import paper_0906_3978_amd as wf
+    from oracle import wiener as ow
+    wl = synth.workload(name)
+    tol = 1e-10 if name == "pl32" else 1e-6
+    ptab = wl.ptab()
+    w = wl.mask()
+    cat = wl.catalogue(ptab, w)
+    dev = torch.device("cuda:0")
+    ctx = wf.Context(0)
+    ctx.set_grid(wl.n, wl.box)
+    ctx.set_mask(torch.from_numpy(w).to(dev))
+    ctx.set_power(torch.from_numpy(ptab).to(dev))
+    xyz = torch.from_numpy(cat.xyz).to(dev)
+    out = torch.empty((wl.n,) * 3, dtype=torch.float64, device=dev)
+
+    def one():
+        ctx.set_galaxies(xyz)
+        ctx.deposit(wl.scheme, wl.supersample)
+        return ctx.solve(out=out, precision="fp64", tol=tol, max_iter=100000)[1]
+    one()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    ts, info = [], None
+    for _ in range(reps):
+        t = time.perf_counter()
+        info = one()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    ctx.close()
+    t_gpu = float(np.median(ts))
+    res = {"workload": f"{name}: {wl.n}^3 / {wl.box:.0f} Mpc, {wl.spectrum}, "
+                       f"{wl.scheme.upper()} s={wl.supersample}, {len(cat.xyz)} galaxies, "
+                       f"plain FP64 CG to {tol:g}",
+           "solves_per_s": round(1.0 / t_gpu, 3), "solve_s_median": round(t_gpu, 5),
+           "iters": info.iters_total, "rel_res_true": info.rel_res_true,
+           "roofline_iteration_fp64": _iteration_roofline(prof, PLAIN_F64, wl.n),
+           "dominant_fp64_kernel": _dominant(prof, PLAIN_F64)}
+    if cpu_full:
+        tc = []
+        for _ in range(3):
+            t = time.perf_counter()
+            r = ow.reconstruct(cat.xyz, wl.n, wl.box, w, ptab, wl.scheme, wl.supersample, tol,
+                               100000)
+            tc.append(time.perf_counter() - t)
+        res["cpu_oracle"] = {"value": round(1.0 / float(np.median(tc)), 4), "unit": "solves/s",
+                             "cores": 1, "kind": "oracle",
+                             "sample": f"full oracle solves (deposit, data vector, {r['iterations']} "
+                                       f"CG iterations), median of 3: "
+                                       f"{', '.join(f'{x:.2f}' for x in tc)} s"}
+    else:
+        res["cpu_oracle"] = cpu_baseline(wl, ptab, w, cat.xyz, info.iters_total, "none")
+    res["speedup_vs_cpu_oracle"] = round(res["solves_per_s"] / res["cpu_oracle"]["value"], 1)
+    log(f"[{name}] {res}")
+    return res
 
 
 def host_cpu():
@@ -125,25 +228,49 @@ def host_cpu():
     return {"model": model, "nproc": os.cpu_count()}
 
 
-def serve(n_req, tol, precond="prior", seed=5000):
-    """Serving stream: requests drawn by synth.serving_request (grids 64..384,
-    random caps, radial scales, spectrum amplitudes and catalogue sizes).
-    Phase A serves them one at a time (isolated capacity, and the reference
-    results); phase B replays them with Poisson arrivals at 0.7 x that
-    capacity through the continuous-batching server.  Every result of B must
-    equal its phase-A result bit for bit."""
+def _pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs), max(1, math.ceil(q * len(xs))))
+    return xs[k - 1]
+
+
+def serve(n_req, tol, precond="prior", seed=5000, per_grid=6, warmup=20, outstanding=48,
+          streams=4):
+    """Serving: a stream of reconstruction requests through the
+    continuous-batching server.
+
+    Requests are drawn with replacement from a pool of `per_grid` distinct
+    request templates per grid size (synth.serving_request: grids 64..384,
+    random caps, radial scales, spectrum amplitudes and catalogue sizes), so
+    that every result can be checked against the same template served alone.
+      A. isolated: every template alone (one at a time) -- reference results
+         and the isolated service time; capacity = 1 / mean service time of
+         the stream's mix;
+      B. Poisson arrivals at 0.7 x capacity: `warmup` requests, then `n_req`
+         measured ones; latency (submit -> result on the host) p50 / p99
+         overall and per grid size, served solves/s;
+      C. saturated: the same `n_req` requests kept `outstanding` at a time
+         (closed loop), solves/s and the batched solves formed.
+    Every result of B and C must equal its template's result of A bit for bit."""
     import synth
     import paper_0906_3978_amd as wf
+    grids = (64, 128, 256, 384)
     t = time.perf_counter()
-    reqs = []
-    for i in range(n_req):
+    templ = []
+    counts = {g: 0 for g in grids}
+    i = 0
+    while min(counts.values()) < per_grid:
         wl = synth.serving_request(i, base_seed=seed + 1)
+        i += 1
+        if counts[wl.n] >= per_grid:
+            continue
+        counts[wl.n] += 1
         ptab = wl.ptab()
         w = wl.mask()
-        cat = wl.catalogue(ptab, w)
-        reqs.append((wl, w, ptab, cat.xyz))
-    log(f"[serve] generated {n_req} requests ({time.perf_counter() - t:.1f} s), grids "
-        f"{sorted(set(r[0].n for r in reqs))}")
+        templ.append((wl, w, ptab, wl.catalogue(ptab, w).xyz))
+    log(f"[serve] {len(templ)} request templates ({time.perf_counter() - t:.1f} s)")
     budget = 96 << 30
     kw = dict(precision="mixed", tol=tol, max_iter=100000, precond=precond)
 
@@ -151,39 +278,86 @@ def serve(n_req, tol, precond="prior", seed=5000):
         wl, w, ptab, xyz = r
         return srv.submit(wl.n, wl.box, w, ptab, xyz, wl.scheme, wl.supersample, **kw)
 
-    alone = []
+    # A: isolated
+    alone, service = [], []
     with wf.Server(0, hbm_budget=budget, max_active=1) as srv:
-        t0 = time.perf_counter()
-        for r in reqs:
+        for r in templ:
+            t0 = time.perf_counter()
             x, info = srv.wait(submit(srv, r), r[0].n, timeout=600)
-            alone.append((hashlib.sha256(x.tobytes()).hexdigest(), info))
-        t_alone = time.perf_counter() - t0
-    cap = n_req / t_alone
-    rate = 0.7 * cap
+            service.append(time.perf_counter() - t0)
+            alone.append(hashlib.sha256(x.tobytes()).hexdigest())
     rng = np.random.Generator(np.random.PCG64(seed))
-    gaps = rng.exponential(1.0 / rate, size=n_req)
-    with wf.Server(0, hbm_budget=budget, max_active=8) as srv:
+    pick = rng.integers(0, len(templ), size=warmup + n_req)
+    cap = 1.0 / float(np.mean([service[k] for k in pick[warmup:]]))
+    rate = 0.7 * cap
+    gaps = rng.exponential(1.0 / rate, size=len(pick))
+
+    def collect(srv, tickets, ks):
+        out = []
+        for tk, k in zip(tickets, ks):
+            x, info = srv.wait(tk, templ[k][0].n, timeout=600)
+            out.append((k, hashlib.sha256(x.tobytes()).hexdigest(), info))
+        return out
+
+    # B: Poisson arrivals
+    with wf.Server(0, hbm_budget=budget, max_active=streams) as srv:
         tickets = []
         t0 = time.perf_counter()
         next_t = 0.0
-        for r, g in zip(reqs, gaps):
+        for k, g in zip(pick, gaps):
             next_t += g
             while time.perf_counter() - t0 < next_t:
                 time.sleep(0.0002)
-            tickets.append(submit(srv, r))
-        outs = []
-        for tk, r in zip(tickets, reqs):
-            x, info = srv.wait(tk, r[0].n, timeout=600)
-            outs.append((hashlib.sha256(x.tobytes()).hexdigest(), info))
-        st = srv.stats()
-    same = all(a[0] == b[0] for a, b in zip(alone, outs))
-    worst = max(b[1].rel_res_true for b in outs)
-    res = {"requests": n_req, "grids": sorted(set(r[0].n for r in reqs)),
+            tickets.append(submit(srv, templ[k]))
+        res_b = collect(srv, tickets, pick)
+        span_b = time.perf_counter() - t0
+        st_b = srv.stats()
+    meas = res_b[warmup:]
+    t_first = sum(gaps[:warmup])
+    lat = [info.latency_ms for _, _, info in meas]
+    per_grid_lat = {}
+    for g in grids:
+        lg = [info.latency_ms for k, _, info in meas if templ[k][0].n == g]
+        if lg:
+            per_grid_lat[str(g)] = {"requests": len(lg), "p50_ms": round(_pct(lg, 0.5), 2),
+                                    "p99_ms": round(_pct(lg, 0.99), 2)}
+    # C: saturated, closed loop
+    import collections
+    with wf.Server(0, hbm_budget=budget, max_active=streams) as srv:
+        inflight = collections.deque()
+        res_c = []
+        t0 = time.perf_counter()
+        for k in pick[warmup:]:
+            if len(inflight) >= outstanding:
+                tk, kk = inflight.popleft()
+                res_c += collect(srv, [tk], [kk])
+            inflight.append((submit(srv, templ[k]), k))
+        while inflight:
+            tk, kk = inflight.popleft()
+            res_c += collect(srv, [tk], [kk])
+        span_c = time.perf_counter() - t0
+        st_c = srv.stats()
+    same = all(h == alone[k] for k, h, _ in res_b + res_c)
+    errs = [info.last_change for _, _, info in res_b + res_c]
+    res = {"requests": n_req, "warmup": warmup, "templates": len(templ), "grids": list(grids),
+           "streams": streams,
+           "isolated_service_ms_per_grid": {str(g): round(1e3 * float(np.mean(
+               [service[j] for j in range(len(templ)) if templ[j][0].n == g])), 2) for g in grids},
            "isolated_solves_per_s": round(cap, 4), "arrival_rate_per_s": round(rate, 4),
-           "solves_per_s": round(st["solves_per_s"], 4), "p50_ms": round(st["p50_ms"], 2),
-           "p99_ms": round(st["p99_ms"], 2), "completed": st["completed"],
-           "failed": st["failed"], "peak_bytes": st["peak_bytes"],
-           "results_equal_alone_and_in_mix": bool(same), "worst_rel_res_true": worst}
+           "served_solves_per_s": round(len(meas) / max(span_b - t_first, 1e-9), 4),
+           "p50_ms": round(_pct(lat, 0.5), 2), "p99_ms": round(_pct(lat, 0.99), 2),
+           "per_grid": per_grid_lat,
+           "batched_solves_poisson": st_b["cohorts"], "largest_batch_poisson": st_b["largest_cohort"],
+           "saturated": {"outstanding": outstanding, "solves_per_s": round(n_req / span_c, 4),
+                         "vs_isolated": round(n_req / span_c / cap, 3),
+                         "batched_solves": st_c["cohorts"],
+                         "largest_batch": st_c["largest_cohort"],
+                         "mean_batch": round(n_req / max(st_c["cohorts"], 1), 2)},
+           "failed": st_b["failed"] + st_c["failed"], "peak_bytes": max(st_b["peak_bytes"],
+                                                                        st_c["peak_bytes"]),
+           "results_equal_alone": bool(same),
+           "worst_last_change": max(errs),
+           "worst_rel_res_true": max(info.rel_res_true for _, _, info in res_b + res_c)}
     log(f"[serve] {res}")
     return res
 
@@ -191,8 +365,11 @@ def serve(n_req, tol, precond="prior", seed=5000):
 def batch_run(nrhs, tol, precond="prior"):
     """Multi-RHS batch: nrhs lognormal-Poisson catalogues of 1e6 galaxies on a
     shared 256^3 / 500 Mpc grid, mask and BBKS prior, CIC 2x supersampled,
-    solved in one mixed-precision batch (every pass one launch for all RHS);
-    compared with the same catalogues solved one at a time."""
+    solved in one mixed-precision batch (every pass one launch for all RHS),
+    with the catalogues already in HBM; per-iteration time and algorithmic
+    bytes of the batched launches from the live profiler; compared with the
+    same catalogues solved one at a time, and the PCIe-inclusive time from
+    host catalogues."""
     import synth
     import torch
     import paper_0906_3978_amd as wf
@@ -205,33 +382,55 @@ def batch_run(nrhs, tol, precond="prior"):
         wl.seed = 4000 + 3 * j
         cats.append(wl.catalogue(ptab, w).xyz)
     log(f"[batch] generated {nrhs} catalogues ({time.perf_counter() - t:.1f} s)")
+    dev = torch.device("cuda:0")
+    dcats = [torch.from_numpy(c).to(dev) for c in cats]
+    outs = [torch.empty((wl.n,) * 3, dtype=torch.float64, device=dev) for _ in range(nrhs)]
     ctx = wf.Context(0)
     ctx.set_grid(wl.n, wl.box)
     ctx.set_mask(w)
     ctx.set_power(ptab)
     kw = dict(precision="mixed", tol=tol, max_iter=100000, precond=precond)
-    ctx.solve_batch(cats[:2], "cic", 2, **kw)  # warm-up
+    ctx.solve_batch(dcats[:2], "cic", 2, outs=outs[:2], **kw)  # warm-up
     torch.cuda.synchronize()
+    ctx.profile_enable(True)
     t = time.perf_counter()
-    outs, infos = ctx.solve_batch(cats, "cic", 2, **kw)
+    _, infos = ctx.solve_batch(dcats, "cic", 2, outs=outs, **kw)
+    torch.cuda.synchronize()
     t_batch = time.perf_counter() - t
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    keys = SPLIT_F32 if precond == "prior" else PLAIN_F32
+    it = _iteration_roofline(prof, keys, wl.n)
+    if it:
+        it["bytes_per_cell_per_rhs"] = round(it["bytes"] / (nrhs * wl.n ** 3), 2)
+        it["model_ms_survey"] = round(76.25 * nrhs * wl.n ** 3 / (HBM_PEAK_GBS * 1e9) * 1e3, 3)
     t = time.perf_counter()
     singles = []
-    for xyz in cats:
+    one = torch.empty((wl.n,) * 3, dtype=torch.float64, device=dev)
+    for xyz in dcats:
         ctx.set_galaxies(xyz)
         ctx.deposit("cic", 2)
-        x, _ = ctx.solve(**kw)
-        singles.append(x)
+        ctx.solve(out=one, **kw)
+        singles.append(hashlib.sha256(one.cpu().numpy().tobytes()).hexdigest())
+    torch.cuda.synchronize()
     t_single = time.perf_counter() - t
-    same = all(np.array_equal(a, b) for a, b in zip(outs, singles))
+    same = all(hashlib.sha256(o.cpu().numpy().tobytes()).hexdigest() == h
+               for o, h in zip(outs, singles))
+    t = time.perf_counter()
+    ctx.solve_batch(cats, "cic", 2, **kw)
+    t_host = time.perf_counter() - t
     iters = [i.iters_total for i in infos]
     res = {"nrhs": nrhs, "n": wl.n, "batch_s": round(t_batch, 3),
            "solves_per_s": round(nrhs / t_batch, 3), "sequential_s": round(t_single, 3),
            "speedup_batch_over_sequential": round(t_single / t_batch, 3),
            "iters_min_max": [min(iters), max(iters)],
+           "iteration": it,
+           "worst_last_change": max(i.last_change for i in infos),
            "worst_rel_res_true": max(i.rel_res_true for i in infos),
            "results_equal_single": bool(same),
-           "note": "host catalogues (PCIe copies inside both timings)"}
+           "host_catalogues_s": round(t_host, 3),
+           "note": "batch_s and sequential_s with the catalogues in HBM; host_catalogues_s "
+                   "includes the PCIe copies"}
     log(f"[batch] {res}")
     ctx.close()
     return res
@@ -383,8 +582,12 @@ def main():
     ap.add_argument("--sd", type=int, default=200,
                     help="also run this many signal-dependent-noise jackknife solves at 128^3 "
                          "(0: skip)")
-    ap.add_argument("--serve", type=int, default=24,
-                    help="also run a serving stream of this many requests (0: skip)")
+    ap.add_argument("--serve", type=int, default=60,
+                    help="also run a serving stream of this many requests after 20 warm-up "
+                         "requests, Poisson and saturated (0: skip)")
+    ap.add_argument("--configs", type=int, default=1,
+                    help="also run the plain FP64 configurations (32^3 power law, 256^3 BBKS) "
+                         "with the oracle beside them (0: skip)")
     ap.add_argument("--batch", type=int, default=16,
                     help="also run the multi-RHS batch: this many 256^3 catalogues in one solve "
                          "(0: skip)")
@@ -552,13 +755,16 @@ def main():
         ctx.solve(out=out, **solve_kw)
         post = post_run(ctx, wl, out)
 
-    cpu = cpu_best = None
+    cpu = None
     if not args.no_cpu_baseline:
         iters_ref = fp64["iters"] if fp64 else info.iters_total
         t = time.perf_counter()
-        cpu, cpu_best = cpu_baseline(wl, ptab, w, len(cat.xyz), iters_ref, args.precond)
-        log(f"[bench] cpu baseline {cpu['value']:.3e} solves/s, best effort "
-            f"{cpu_best['value']:.3e} on {cpu_best['cores']} cores ({time.perf_counter() - t:.1f} s)")
+        cpu = cpu_baseline(wl, ptab, w, cat.xyz, iters_ref, args.precond)
+        log(f"[bench] cpu baseline {cpu['value']:.3e} solves/s on {cpu['cores']} threads "
+            f"({time.perf_counter() - t:.1f} s): {cpu['sample']}")
+
+    c1 = fp64_config_run("pl32", reps=5, cpu_full=True) if args.configs else None
+    c2 = fp64_config_run("bbks256", reps=3) if args.configs else None
 
     serving = serve(args.serve, args.tol, args.precond) if args.serve else None
     batch = batch_run(args.batch, args.tol, args.precond) if args.batch else None
@@ -599,7 +805,8 @@ def main():
         "plain_cg": plain,
         "post": post,
         "cpu_baseline": cpu,
-        "cpu_best_effort": cpu_best,
+        "c1_fp64_32": c1,
+        "c2_fp64_256": c2,
         "serving": serving,
         "batch": batch,
         "signal_dependent": sdres,

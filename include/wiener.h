@@ -119,11 +119,13 @@ typedef struct wf_server wf_server;
  *               convergence by itself.
  *   precond     wf_precond.
  *   err_tol     MIXED only (0: the default 5e-7; < 0: no such condition):
- *               once the FP64 residual meets tol the
- *               solve goes on for at least one more reliable update, and stops
- *               at the first update that meets tol again and changed the
- *               solution s by at most err_tol relative (||s_new - s_old|| /
- *               ||s_new||, on s = C y for the prior-split form).  The residual
+ *               once the FP64 residual meets tol the solve goes on through
+ *               the reliable updates that reduce the residual by another
+ *               factor of 10 (one at the default inner_tol), and stops at the
+ *               first update, with tol met, after which their summed changes
+ *               of the solution s are at most err_tol relative
+ *               (||s_new - s_old|| / ||s_new||, on s = C y for the
+ *               prior-split form).  The residual
  *               alone does not bound the error of a mixed solve: FP32 rounding
  *               of the operator, which grows with nbar, leaves large-scale
  *               error in the unobserved region that the residual barely

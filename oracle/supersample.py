@@ -32,13 +32,18 @@ def crop_spectrum(gk, n):
     return out
 
 
-def lowpass_decimate(g_fine, n):
-    """Real fine field (2n)^3 -> band-limited real field n^3."""
+def lowpass_decimate(g_fine, n, workers=None):
+    """Real fine field (2n)^3 -> band-limited real field n^3.  `workers`:
+    scipy's FFT on that many threads (the same transform as numpy's)."""
+    if workers:
+        import scipy.fft as sf
+        gk = sf.rfftn(g_fine, workers=workers)
+        return sf.irfftn(crop_spectrum(gk, n), s=(n, n, n), axes=(0, 1, 2), workers=workers)
     gk = np.fft.rfftn(g_fine)
     return np.fft.irfftn(crop_spectrum(gk, n), s=(n, n, n), axes=(0, 1, 2))
 
 
-def observed_counts(xyz, n, box, scheme, supersample):
+def observed_counts(xyz, n, box, scheme, supersample, workers=None):
     """n^o on the n^3 target grid, plus the integer deposit it came from.
 
     supersample = 1: the deposit itself (times its unit).
@@ -51,7 +56,7 @@ def observed_counts(xyz, n, box, scheme, supersample):
         return g, grid
     if supersample != 2:
         raise ValueError("supersample must be 1 or 2")
-    return lowpass_decimate(g, n), grid
+    return lowpass_decimate(g, n, workers), grid
 
 
 def lowpass_kernel_1d(t, n):

@@ -60,9 +60,18 @@ struct CgState {
   // bound it must meet, besides the residual tolerance, to stop (0: none)
   double move;
   double err_tol;
-  int32_t hold;      // 1: residual tolerance met, waiting for the change to fall below err_tol
-  int32_t pad_;
+  int32_t hold;      // updates so far, this one included, whose residual met tol
+  int32_t hold_need; // intervals the change is summed over: a residual drop of 10 at delta
+  double move_acc;   // sum of the changes of the updates after the first with the residual met
 };
+
+// Reliable-update intervals that together reduce the recursive residual by
+// at least 10 (each reduces it by delta).
+__host__ __device__ inline int32_t settle_intervals(double delta) {
+  if (!(delta > 0.0) || delta >= 1.0) return 1;
+  const int32_t k = (int32_t)ceil(log(0.1) / log(delta) - 1e-9);
+  return k < 1 ? 1 : k;
+}
 
 // The prior-split factor table is stored in blocks of this many consecutive kz.
 constexpr int SPLIT_FB = 16;

@@ -377,10 +377,19 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const dou
       st->updates += 1;
       st->pending = 0;  // folded
       const double rel = sqrt(st->outer_rr) / st->bnorm;
-      // with err_tol, the residual must already have met tol at the previous
-      // update (hold) and this update's change of the solution, which shows
-      // error the residual had hidden, must be at most err_tol
-      const bool settled = !(st->err_tol > 0.0) || (st->hold && st->move <= st->err_tol);
+      // with err_tol: once the residual meets tol, the solve goes on until the
+      // updates after that one have reduced the residual by 10 (hold_need of
+      // them) and changed the solution by at most err_tol in all: that change
+      // shows the error the residual had hidden
+      if (rel <= st->tol) {
+        if (st->hold > 0) st->move_acc += st->move;
+        st->hold += 1;
+      } else {
+        st->hold = 0;
+        st->move_acc = 0.0;
+      }
+      const bool settled = !(st->err_tol > 0.0) ||
+                           (st->hold > st->hold_need && st->move_acc <= st->err_tol);
       if (rel <= st->tol && settled) {
         st->status = CG_CONVERGED;
       } else if (st->iter >= st->max_iter) {
@@ -391,7 +400,6 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const dou
         // continue from the refreshed residual with the same direction; with
         // the residual met but the solution still moving, the next update
         // comes when the residual has dropped by delta again
-        st->hold = rel <= st->tol ? 1 : 0;
         st->beta = tot / st->rho_old;
         st->rho = tot;
         st->rmax = sqrt(tot);
@@ -424,6 +432,7 @@ __global__ void k_state_init(CgState* st_all, const double* nbar, double tol, in
   z.delta = delta;
   z.max_updates = max_updates;
   z.err_tol = err_tol;
+  z.hold_need = settle_intervals(delta);
   *st = z;
 }
 

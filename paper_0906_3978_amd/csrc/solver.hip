@@ -308,6 +308,7 @@ Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
     st[i].delta = o.inner_tol > 0 ? o.inner_tol : 0.1;
     st[i].max_updates = o.max_outer;
     st[i].err_tol = effective_err_tol(o);
+    st[i].hold_need = settle_intervals(st[i].delta);
   }
   WF_TRY(push_states(sw, st, s));
   Timer tm;

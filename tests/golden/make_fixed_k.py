@@ -7,7 +7,8 @@ deposit, low-pass, data vector) and then, on the plain FP64 system:
 
 * exactly k CG iterations for every k of --ks, and the spread of those
   iterates under the noise model of tests/sensitivity.py (1e-15 relative
-  noise in every transform stage, 1e-14 on the data; two seeds): the
+  noise in every transform stage, 1e-15 of the largest value on the data;
+  two seeds): the
   rounding sensitivity the fixed-k GPU bounds are derived from;
 * CG to the relative residual --tol (the workload's own stopping rule): the
   oracle's result at that stop;

@@ -8,12 +8,16 @@ white noise of EPS times the root mean square of each transformed field is
 added to it -- to the forward spectrum before the Fourier diagonal multiplies
 it (so the forward transform's error is scaled by Lambda, or by the split
 factor, as in any implementation) and to the result of each inverse
-transform -- and the right-hand side gets EPS_B times its own.  A 3D FFT's
-rounding is of that form, about sqrt(log2 M) 1.1e-16 of the field's norm
-spread over every element (5e-16 at 256^3), and EPS = 1e-15 bounds it at the
-sizes tested; EPS_B = 1e-14 bounds the agreement of the gridded data with the
-oracle's (the n^o parity bound is 1e-13 of its maximum).  The perturbed k-th
-iterate is compared with the unperturbed one.
+transform -- and the right-hand side, on its observed cells, EPS_B times its
+largest magnitude.  A 3D FFT's rounding is of that form, about
+sqrt(log2 M) 1.1e-16 of the field's norm spread over every element (5e-16 at
+256^3), and EPS = 1e-15 bounds it at the sizes tested.  The gridded data come
+out of the FFT low-pass, so their rounding is absolute too, of the order of
+the largest count: n^o agrees with the oracle's to 4e-16 of its maximum at
+256^3, and EPS_B = 1e-15 bounds that.  For the lognormal fields of these
+workloads the largest |b| is ~2000 times its root mean square, which makes
+the data's rounding, not the operator's, the larger source at small k.  The
+perturbed k-th iterate is compared with the unperturbed one.
 
 SPREADS holds the spreads measured this way (the larger of two seed pairs)
 for the workloads and iteration counts of the fixed-iteration GPU tests;
@@ -29,20 +33,20 @@ import numpy as np
 from oracle import wiener as ow
 
 EPS = 1e-15
-EPS_B = 1e-14
+EPS_B = 1e-15
 FACTOR = 5.0
 FLOOR = 1e-13
 
 # (workload, form, k) -> relative L2 spread of the k-th iterate
 SPREADS = {
-    ("pl32", "plain", 50): 3.2e-5,
-    ("pl32", "plain", 300): 5.1e-7,
-    ("bbks48", "plain", 50): 5.7e-10,
-    ("bbks48", "plain", 300): 9.7e-13,
-    ("bbks48", "split", 1): 3.6e-15,
-    ("bbks48", "split", 20): 1.5e-9,
-    ("bbks48", "split", 80): 2.1e-8,
-    ("bbks48", "split", 200): 1.4e-13,
+    ("pl32", "plain", 50): 3.1e-5,
+    ("pl32", "plain", 300): 2.0e-6,
+    ("bbks48", "plain", 50): 6.9e-10,
+    ("bbks48", "plain", 300): 2.6e-13,
+    ("bbks48", "split", 1): 8.7e-15,
+    ("bbks48", "split", 20): 2.0e-9,
+    ("bbks48", "split", 80): 2.4e-8,
+    ("bbks48", "split", 200): 4.6e-14,
 }
 
 
@@ -109,10 +113,13 @@ class PerturbedSplit:
 
 
 def perturbed_rhs(b, seed, eps=EPS_B):
-    """b plus white noise of eps times its root mean square (seeded)."""
+    """b plus white noise of eps times its largest magnitude on the cells where
+    it is not zero (seeded): the rounding of a gridded field produced by FFTs
+    is absolute, of the order of the largest value."""
     b = np.asarray(b, dtype=np.float64)
     rng = np.random.Generator(np.random.PCG64(1000 + seed))
-    return b + (eps * _rms(b)) * rng.standard_normal(b.shape)
+    noise = (eps * float(np.abs(b).max())) * rng.standard_normal(b.shape)
+    return b + np.where(b != 0.0, noise, 0.0)
 
 
 def rel_l2(a, b):

@@ -32,3 +32,23 @@ def test_traffic_follows_the_kernel_sources():
 def test_host_cpu():
     h = bench.host_cpu()
     assert h["nproc"] >= 1
+
+
+def test_cpu_baseline_phases_on_a_small_workload():
+    """The oracle's per-phase timing on a 16^3 version of the headline recipe:
+    every phase is timed, the CG iteration is extrapolated and labelled."""
+    import synth
+    wl = synth.workload("bbks512", n=16)
+    wl.n_target = 5000
+    ptab = wl.ptab()
+    w = wl.mask()
+    xyz = wl.catalogue(ptab, w).xyz
+    for precond in ("prior", "none"):
+        base = bench.cpu_baseline(wl, ptab, w, xyz, 40, precond, cg_iters=4)
+        ph = base["phases_s"]
+        assert base["kind"] == "oracle" and base["extrapolated"]
+        assert base["cores"] >= 1 and base["value"] > 0
+        assert ph["cg_iterations_timed"] == 4 and ph["cg_iterations_extrapolated"] == 40
+        assert min(ph["deposit"], ph["lowpass"], ph["cg_iteration"]) > 0
+        total = ph["deposit"] + ph["lowpass"] + ph["data_vector"] + 40 * ph["cg_iteration"]
+        assert abs(1.0 / base["value"] - total) < 0.01 * total + 1e-3

@@ -53,7 +53,7 @@ def bbks48():
     """48^3 / 500 Mpc, BBKS prior, 60 deg cap with exp(-r/150 Mpc), lognormal
     Poisson catalogue with 2x supersampled CIC: a problem whose fixed-k CG
     iterates are stable under rounding (the oracle's own iterate moves by
-    3e-9 at k = 50 and 8e-13 at k = 300 under rounding-sized noise,
+    7e-10 at k = 50 and 3e-13 at k = 300 under rounding-sized noise,
     tests/sensitivity.py)."""
     wl = synth.Workload("bbks48", 48, 500.0, "cic", 2, 60000, 211, "bbks")
     ptab = wl.ptab()
@@ -90,7 +90,7 @@ def test_fixed_iteration_parity_fp64(ctx, bbks48, k):
 def test_fixed_iteration_parity_powerlaw(ctx, pl32, k):
     """The power law with its Gaussian cut-off isolates the largest
     eigenvalues (the corner modes); fixed-k CG iterates are rounding-chaotic
-    there: the oracle's own k-th iterate moves by 3e-5 (k = 50) and 1.9e-6
+    there: the oracle's own k-th iterate moves by 3e-5 (k = 50) and 2e-6
     (k = 300) under rounding-sized noise (tests/sensitivity.py), and the
     bound is a multiple of that; the converged comparison below is the tight
     one."""

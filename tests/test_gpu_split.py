@@ -48,9 +48,9 @@ def _load(ctx, d):
 def test_fixed_iteration_parity_split_fp64(ctx, bbks48, k):
     """Both sides run exactly k iterations of CG on C A C from y = 0.  The
     bound is a multiple of the oracle's own spread at that k under
-    rounding-sized noise (tests/sensitivity.py): its iterates move by 9e-10
-    at k = 20, 2.3e-8 at k = 80 (the phase where the large eigenvalues are
-    being resolved) and 3e-14 at k = 200."""
+    rounding-sized noise (tests/sensitivity.py): its iterates move by 2e-9
+    at k = 20, 2.4e-8 at k = 80 (the phase where the large eigenvalues are
+    being resolved) and 5e-14 at k = 200."""
     tol = se.bound("bbks48", "split", k)
     d = bbks48
     _load(ctx, d)

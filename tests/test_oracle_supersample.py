@@ -124,3 +124,13 @@ def test_supersample_one_is_plain_deposit():
     n_obs, grid = oss.observed_counts(xyz, 8, 64.0, "cic", 1)
     assert np.array_equal(grid, od.deposit(xyz, 8, 64.0, "cic"))
     assert np.allclose(n_obs, grid * 2.0 ** -39, rtol=0, atol=0)
+
+
+def test_threaded_fft_route_is_the_same_lowpass():
+    """The optional multi-threaded FFT (scipy) gives the numpy route's field to
+    rounding: the same transform, only the library differs."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    g = rng.standard_normal((24, 24, 24))
+    a = oss.lowpass_decimate(g, 12)
+    b = oss.lowpass_decimate(g, 12, workers=4)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
