@@ -156,6 +156,10 @@ typedef struct {
                                  an estimate of the error left; 0 for FP64    */
   double latency_ms;          /* server: submit -> result ready on the host;
                                  0 elsewhere                                  */
+  int32_t stagnated;          /* MIXED: 1 if the solve stopped (WF_ENOTCONV)
+                                 because its FP64 residual fell by less than a
+                                 factor 2 at 3 reliable updates in a row: tol
+                                 is below what the arithmetic reaches        */
 } wf_solve_info;
 
 /* ---- library ----------------------------------------------------------- */
@@ -226,15 +230,19 @@ wf_status wf_forward_spectrum(wf_ctx* ctx, wf_precision prec, const double* v,
 wf_status wf_solve(wf_ctx* ctx, const wf_solve_opts* opts, double* s_out,
                    wf_mem mem, wf_solve_info* info);
 
-/* Krylov state of an FP64 solve (plain or prior-split), for checkpoint /
- * resume.  wf_solve_begin starts an FP64 solve, wf_solve_step runs up to
- * `iters` iterations, wf_solve_snapshot copies the state (x, r, p and scalars;
- * half spectra for the prior-split form) into host_buf of wf_snapshot_bytes()
- * bytes (the size for the active solve; without one, that of a plain solve),
- * wf_solve_resume restores it into a context with the same grid, mask, power
- * and rhs (the snapshot records its form), and wf_solve_finish writes s and
- * info.  Continuing from a snapshot gives bit-identical results, equal to an
- * uninterrupted wf_solve of as many iterations. */
+/* Krylov state of a solve (FP64 or mixed, plain or prior-split), for
+ * checkpoint / resume.  wf_solve_begin starts a solve, wf_solve_step runs up
+ * to `iters` more CG iterations (mixed: FP32 iterations, with the reliable
+ * updates they call for), wf_solve_snapshot copies the state into host_buf of
+ * wf_snapshot_bytes() bytes (the size for the active solve; without one, that
+ * of a plain FP64 solve): the scalars and x, r, p in FP64, or for a mixed
+ * solve the FP64 x and r and the FP32 x, r, p -- half spectra for the
+ * prior-split form.  wf_solve_resume restores it into a context with the same
+ * grid, mask, power and rhs (the snapshot records its form), and
+ * wf_solve_finish writes s and info (a mixed solve stopped between reliable
+ * updates first folds its FP32 correction and takes the FP64 residual, as an
+ * update would).  Continuing from a snapshot gives bit-identical results,
+ * equal to an uninterrupted wf_solve of as many iterations. */
 wf_status wf_solve_begin(wf_ctx* ctx, const wf_solve_opts* opts);
 wf_status wf_solve_step(wf_ctx* ctx, int32_t iters, int32_t* done);
 size_t wf_snapshot_bytes(const wf_ctx* ctx);

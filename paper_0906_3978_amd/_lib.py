@@ -38,7 +38,8 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters_total", C.c_int32), ("outer_steps", C.c_int32),
                 ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double),
                 ("time_ms", C.c_double), ("model_bytes", C.c_double), ("nbar", C.c_double),
-                ("status", C.c_int32), ("last_change", C.c_double), ("latency_ms", C.c_double)]
+                ("status", C.c_int32), ("last_change", C.c_double), ("latency_ms", C.c_double),
+                ("stagnated", C.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -234,6 +235,7 @@ class Info:
     status: int
     last_change: float
     latency_ms: float
+    stagnated: int
     status_name: str
 
 

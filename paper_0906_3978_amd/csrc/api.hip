@@ -26,6 +26,7 @@ struct wf_ctx {
   DepositWork dw;
   SolveWork sw;
   bool solve_active = false;
+  bool active_mixed = false;
   wf_solve_opts active_opts{};
   double active_ms = 0.0;
   Profiler prof;
@@ -436,12 +437,12 @@ wf_status wf_solve_begin(wf_ctx* c, const wf_solve_opts* opts) {
   Status s = need(c->have_grid && c->have_mask && c->have_power && c->have_rhs,
                   "wf_solve_begin needs grid, mask, power and a data vector");
   if (!s.ok()) return finish(c, s);
-  if (opts->precision != WF_FP64) return finish(c, fail(WF_EINVAL, "stepwise solves are FP64"));
   s = validate_opts(*opts);
   if (s.ok()) s = set_device(c);
   if (s.ok() && opts->precond == WF_PRECOND_PRIOR) s = ensure_split_fac(c->al, c->od, c->stream);
-  if (s.ok()) s = fp64_begin(c->od, c->al, c->sw, c->nbar, *opts, c->stream);
+  if (s.ok()) s = step_begin(c->od, c->al, c->sw, c->nbar, *opts, c->stream);
   c->solve_active = s.ok();
+  c->active_mixed = opts->precision == WF_MIXED;
   c->active_opts = *opts;
   c->active_ms = 0.0;
   return finish(c, s);
@@ -452,7 +453,7 @@ wf_status wf_solve_step(wf_ctx* c, int32_t iters, int32_t* done) {
   Status s = need(c->solve_active, "wf_solve_begin or wf_solve_resume first");
   if (!s.ok()) return finish(c, s);
   s = set_device(c);
-  if (s.ok()) s = fp64_iterations(c->od, c->sw, iters, c->stream);
+  if (s.ok()) s = step_iterations(c->od, c->sw, iters, c->active_mixed, c->stream);
   if (s.ok()) s = c->sw.pull_state(c->stream);
   if (s.ok() && done) *done = c->sw.st_host[0].done;
   return finish(c, s);
@@ -460,17 +461,18 @@ wf_status wf_solve_step(wf_ctx* c, int32_t iters, int32_t* done) {
 
 size_t wf_snapshot_bytes(const wf_ctx* c) {
   if (!c || !c->have_grid) return 0;
-  return snapshot_bytes(c->od.g, c->solve_active && c->sw.split);
+  return snapshot_bytes(c->od.g, c->solve_active && c->sw.split,
+                        c->solve_active && c->active_mixed);
 }
 
 wf_status wf_solve_snapshot(wf_ctx* c, void* buf, size_t bytes) {
   if (!c || !buf) return c ? finish(c, fail(WF_EINVAL, "null buffer")) : WF_EINVAL;
   Status s = need(c->solve_active, "no active solve");
   if (!s.ok()) return finish(c, s);
-  if (bytes < snapshot_bytes(c->od.g, c->sw.split))
+  if (bytes < snapshot_bytes(c->od.g, c->sw.split, c->active_mixed))
     return finish(c, fail(WF_EINVAL, "snapshot buffer too small"));
   s = set_device(c);
-  if (s.ok()) s = snapshot_save(c->od.g, c->sw, buf, c->stream);
+  if (s.ok()) s = snapshot_save(c->od.g, c->sw, c->active_mixed, buf, c->stream);
   return finish(c, s);
 }
 
@@ -479,14 +481,16 @@ wf_status wf_solve_resume(wf_ctx* c, const void* buf, size_t bytes) {
   Status s = need(c->have_grid && c->have_mask && c->have_power && c->have_rhs,
                   "resume needs grid, mask, power and a data vector");
   if (!s.ok()) return finish(c, s);
-  if (bytes < snapshot_bytes(c->od.g, false)) return finish(c, fail(WF_EINVAL, "snapshot buffer too small"));
-  const bool split = snapshot_split(buf);
-  if (bytes < snapshot_bytes(c->od.g, split))
+  bool split = false, mixed = false;
+  if (bytes < snapshot_bytes(c->od.g, false, false) || !snapshot_kind(buf, &split, &mixed))
+    return finish(c, fail(WF_EINVAL, "not a snapshot of this library"));
+  if (bytes < snapshot_bytes(c->od.g, split, mixed))
     return finish(c, fail(WF_EINVAL, "snapshot buffer too small"));
   s = set_device(c);
   if (s.ok() && split) s = ensure_split_fac(c->al, c->od, c->stream);
   if (s.ok()) s = snapshot_load(c->od, c->al, c->sw, buf, c->stream);
   c->solve_active = s.ok();
+  c->active_mixed = mixed;
   return finish(c, s);
 }
 
@@ -496,7 +500,7 @@ wf_status wf_solve_finish(wf_ctx* c, double* s_out, wf_mem mem, wf_solve_info* i
   if (!s.ok()) return finish(c, s);
   wf_solve_info inf{};
   s = set_device(c);
-  if (s.ok()) s = fp64_finish(c->od, c->sw, c->stream, &inf);
+  if (s.ok()) s = step_finish(c->od, c->sw, c->active_mixed, c->stream, &inf);
   if (s.ok() || s.code == WF_ENOTCONV) {
     Status d = download(s_out, c->sw.x64.p, (size_t)c->od.g.m * 8, mem, c->stream);
     if (!d.ok()) return finish(c, d);

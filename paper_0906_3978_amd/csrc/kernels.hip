@@ -390,12 +390,17 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const dou
       }
       const bool settled = !(st->err_tol > 0.0) ||
                            (st->hold > st->hold_need && st->move_acc <= st->err_tol);
+      st->stall = (st->updates > 1 && !(rel < 0.5 * st->prev_rel)) ? st->stall + 1 : 0;
+      st->prev_rel = rel;
       if (rel <= st->tol && settled) {
         st->status = CG_CONVERGED;
       } else if (st->iter >= st->max_iter) {
         st->status = CG_MAXITER;
       } else if (st->max_updates > 0 && st->updates >= st->max_updates) {
         st->status = CG_STOPPED;
+      } else if (st->stall >= STALL_UPDATES) {
+        st->status = CG_STOPPED;
+        st->stagnated = 1;
       } else {
         // continue from the refreshed residual with the same direction; with
         // the residual met but the solution still moving, the next update
@@ -451,6 +456,20 @@ __global__ void k_state_stop(CgState* st) {
     st->done = 1;
     st->status = CG_STOPPED;
   }
+}
+
+// A running mixed solve asks for a reliable update now (the stepwise API's
+// finish between updates).
+__global__ void k_state_request_update(CgState* st) {
+  if (threadIdx.x == 0 && !st->done) {
+    st->done = 1;
+    st->status = CG_UPDATE;
+  }
+}
+
+hipError_t launch_state_request_update(CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_request_update, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
 }
 
 hipError_t launch_state_stop(CgState* st, hipStream_t s) {

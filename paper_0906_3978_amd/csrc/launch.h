@@ -168,6 +168,8 @@ hipError_t launch_state_init(CgState* st, const double* nbar, double tol, int32_
                              double delta, int32_t max_updates, double err_tol, int nrhs,
                              hipStream_t s);
 
+// a running mixed solve: ask for a reliable update (done, CG_UPDATE)
+hipError_t launch_state_request_update(CgState* st, hipStream_t s);
 // marks one solve stopped (done, CG_STOPPED)
 hipError_t launch_state_stop(CgState* st, hipStream_t s);
 

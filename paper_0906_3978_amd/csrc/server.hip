@@ -30,6 +30,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.h"
+#include "checks.h"
 #include "internal.h"
 #include "solver.h"
 
@@ -42,66 +44,6 @@ using Clock = std::chrono::steady_clock;
 double ms_between(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double, std::milli>(b - a).count();
 }
-
-// First-fit arena over one device allocation; 256-byte granules.
-struct Arena {
-  char* base = nullptr;
-  size_t size = 0;
-  std::mutex mu;
-  std::map<size_t, size_t> free_;   // offset -> bytes
-  std::map<size_t, size_t> used_;   // offset -> bytes
-  size_t in_use = 0, peak = 0;
-
-  void init(void* p, size_t n) {
-    base = static_cast<char*>(p);
-    size = n & ~size_t(255);
-    free_.clear();
-    used_.clear();
-    free_[0] = size;
-    in_use = peak = 0;
-  }
-  void* get(size_t bytes) {
-    bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
-    std::lock_guard<std::mutex> g(mu);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < bytes) continue;
-      const size_t off = it->first, left = it->second - bytes;
-      free_.erase(it);
-      if (left) free_[off + bytes] = left;
-      used_[off] = bytes;
-      in_use += bytes;
-      peak = std::max(peak, in_use);
-      return base + off;
-    }
-    return nullptr;
-  }
-  void put(void* p) {
-    if (!p) return;
-    std::lock_guard<std::mutex> g(mu);
-    const size_t off = static_cast<char*>(p) - base;
-    auto u = used_.find(off);
-    if (u == used_.end()) return;
-    size_t len = u->second;
-    used_.erase(u);
-    in_use -= len;
-    size_t start = off;
-    auto nx = free_.lower_bound(off);
-    if (nx != free_.end() && nx->first == off + len) {
-      len += nx->second;
-      free_.erase(nx);
-    }
-    auto pv = free_.lower_bound(off);
-    if (pv != free_.begin()) {
-      --pv;
-      if (pv->first + pv->second == off) {
-        start = pv->first;
-        len += pv->second;
-        free_.erase(pv);
-      }
-    }
-    free_[start] = len;
-  }
-};
 
 void* arena_alloc(size_t bytes, void* user) { return static_cast<Arena*>(user)->get(bytes); }
 void arena_free(void* p, void* user) { static_cast<Arena*>(user)->put(p); }
@@ -215,32 +157,8 @@ struct wf_server {
 namespace {
 
 Status validate_request(const wf_request& r) {
-  Grid g;
-  int m = r.n;
-  if (r.n < 8 || r.n > 512) return fail(WF_EINVAL, "n out of range");
-  while (m % 2 == 0) m /= 2;
-  if (m != 1 && m != 3) return fail(WF_EINVAL, "n must be 2^a 3^b (b <= 1)");
-  if (!(r.box_mpc > 0.0) || !std::isfinite(r.box_mpc)) return fail(WF_EINVAL, "bad box");
-  if (!r.w || !r.p_by_m2 || (r.n_gal > 0 && !r.xyz) || r.n_gal < 0)
-    return fail(WF_EINVAL, "null request array");
-  if (r.n_gal >= (int64_t(1) << 24)) return fail(WF_EOVERFLOW, "n_gal must be < 2^24");
-  if (r.scheme < WF_NGP || r.scheme > WF_TSC || (r.supersample != 1 && r.supersample != 2))
-    return fail(WF_EINVAL, "bad scheme or supersample");
-  WF_TRY(validate_opts(r.opts));
-  g.set(r.n, r.box_mpc);
-  double sw = 0.0;
-  for (int64_t i = 0; i < g.m; ++i) {
-    const double v = r.w[i];
-    if (!(v >= 0.0 && v <= 1.0)) return fail(WF_EINVAL, "mask values must be in [0, 1]");
-    sw += v;
-  }
-  if (!(sw > 0.0)) return fail(WF_EINVAL, "mask is zero everywhere");
-  for (int64_t j = 1; j < g.lamlen; ++j)
-    if (!(r.p_by_m2[j] > 0.0) || !std::isfinite(r.p_by_m2[j]))
-      return fail(WF_EINVAL, "P(k) must be finite and > 0");
-  for (int64_t i = 0; i < 3 * r.n_gal; ++i)
-    if (!(r.xyz[i] >= 0.0 && r.xyz[i] < r.box_mpc))
-      return fail(WF_EINVAL, "galaxy coordinates must satisfy 0 <= x < L");
+  wf_status code = WF_OK;
+  if (const char* e = request_error(r, &code)) return fail(code, e);
   return {};
 }
 

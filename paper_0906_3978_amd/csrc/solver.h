@@ -40,14 +40,21 @@ Status solve_finish(const OperatorData& od, SolveWork& sw, int nr, bool mixed, h
 void solve_infos(const CgState* st, int nr, bool mixed, bool split, const Grid& g, double ms,
                  wf_solve_info* infos);
 
-// Stepwise FP64 solve of one RHS (checkpoint / resume), plain or prior-split.
-Status fp64_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, double nbar,
+// Stepwise solve of one RHS (checkpoint / resume), FP64 or mixed, plain or
+// prior-split.  step_iterations runs `iters` more CG iterations (mixed: FP32
+// iterations, with the reliable updates the state asks for); step_finish
+// (mixed: after folding a pending FP32 correction) writes s into x64.
+Status step_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, double nbar,
                   const wf_solve_opts& o, hipStream_t s);
-Status fp64_iterations(const OperatorData& od, SolveWork& sw, int iters, hipStream_t s);
-Status fp64_finish(const OperatorData& od, SolveWork& sw, hipStream_t s, wf_solve_info* info);
-size_t snapshot_bytes(const Grid& g, bool split);
-bool snapshot_split(const void* buf);  // header of a snapshot (at least its header's bytes)
-Status snapshot_save(const Grid& g, SolveWork& sw, void* buf, hipStream_t s);
+Status step_iterations(const OperatorData& od, SolveWork& sw, int iters, bool mixed,
+                       hipStream_t s);
+Status step_finish(const OperatorData& od, SolveWork& sw, bool mixed, hipStream_t s,
+                   wf_solve_info* info);
+size_t snapshot_bytes(const Grid& g, bool split, bool mixed);
+// the form of a snapshot from its header (at least its header's bytes); false
+// if it is not a snapshot
+bool snapshot_kind(const void* buf, bool* split, bool* mixed);
+Status snapshot_save(const Grid& g, SolveWork& sw, bool mixed, void* buf, hipStream_t s);
 Status snapshot_load(const OperatorData& od, const Allocator& al, SolveWork& sw, const void* buf,
                      hipStream_t s);
 

@@ -17,19 +17,14 @@
 #include <cstring>
 #include <vector>
 
+#include "checks.h"
 #include "solver.h"
 
 namespace wf {
 
 Status validate_opts(const wf_solve_opts& o) {
-  if (o.precision != WF_FP64 && o.precision != WF_MIXED) return fail(WF_EINVAL, "unknown precision");
-  if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(WF_EINVAL, "tol must be finite and >= 0");
-  if (o.max_iter < 0) return fail(WF_EINVAL, "max_iter must be >= 0");
-  if (!(o.inner_tol >= 0.0) || o.inner_tol >= 1.0) return fail(WF_EINVAL, "inner_tol must be in [0, 1)");
-  if (o.max_outer < 0 || o.check_every < 0) return fail(WF_EINVAL, "max_outer and check_every must be >= 0");
-  if (o.precond != WF_PRECOND_NONE && o.precond != WF_PRECOND_PRIOR)
-    return fail(WF_EINVAL, "unknown precond");
-  if (!std::isfinite(o.err_tol)) return fail(WF_EINVAL, "err_tol must be finite");
+  wf_status code = WF_OK;
+  if (const char* e = opts_error(o, &code)) return fail(code, e);
   return {};
 }
 
@@ -285,6 +280,7 @@ void solve_infos(const CgState* st, int nr, bool mixed, bool split, const Grid& 
     in.nbar = c.nbar;
     in.status = map_cg_status(c.status);
     in.last_change = mixed ? c.move : 0.0;
+    in.stagnated = c.stagnated;
   }
 }
 
@@ -329,32 +325,70 @@ Status run_solve(const SolveRequest& rq, wf_solve_info* infos) {
   return worst;
 }
 
-// ---- stepwise FP64 solve ---------------------------------------------------
+// ---- stepwise solve (checkpoint / resume) ---------------------------------
 
-Status fp64_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, double nbar,
+Status step_begin(const OperatorData& od, const Allocator& al, SolveWork& sw, double nbar,
                   const wf_solve_opts& o, hipStream_t s) {
-  WF_TRY(sw.ensure(al, od.g, 1, true, false, o.precond == WF_PRECOND_PRIOR));
+  const bool mixed = o.precision == WF_MIXED;
+  WF_TRY(sw.ensure(al, od.g, 1, !mixed, mixed, o.precond == WF_PRECOND_PRIOR));
   std::vector<CgState> st(1);
   st[0] = CgState{};
   st[0].nbar = nbar;
   st[0].tol = o.tol;
   st[0].max_iter = o.max_iter;
+  st[0].delta = o.inner_tol > 0 ? o.inner_tol : 0.1;
+  st[0].max_updates = o.max_outer;
+  st[0].err_tol = effective_err_tol(o);
+  st[0].hold_need = settle_intervals(st[0].delta);
   WF_TRY(push_states(sw, st, s));
-  return solve_start(od, sw, 1, false, s);
+  return solve_start(od, sw, 1, mixed, s);
 }
 
-Status fp64_iterations(const OperatorData& od, SolveWork& sw, int iters, hipStream_t s) {
-  Vecs<double> v = v64(sw);
-  for (int k = 0; k < iters; ++k) WF_TRY(any_iteration<double>(od, sw, v, 1, s));
-  return {};
+Status step_iterations(const OperatorData& od, SolveWork& sw, int iters, bool mixed,
+                       hipStream_t s) {
+  if (!mixed) {
+    Vecs<double> v = v64(sw);
+    for (int k = 0; k < iters; ++k) WF_TRY(any_iteration<double>(od, sw, v, 1, s));
+    return {};
+  }
+  // FP32 iterations until `iters` more have run or the solve stops, with the
+  // reliable updates the state asks for on the way (the device decides when;
+  // how the host chunks its launches changes nothing)
+  WF_TRY(sw.pull_state(s));
+  const int64_t target = (int64_t)sw.st_host[0].iter + iters;
+  Vecs<float> v = v32(sw);
+  for (;;) {
+    const CgState& c = sw.st_host[0];
+    if (c.iter >= target) return {};
+    if (c.status == CG_UPDATE) {
+      WF_TRY(solve_update(od, sw, 1, s));
+    } else if (c.done) {
+      return {};
+    } else {
+      const int64_t left = target - c.iter;
+      for (int64_t k = 0; k < std::min<int64_t>(left, 16); ++k)
+        WF_TRY(any_iteration<float>(od, sw, v, 1, s));
+    }
+    WF_TRY(sw.pull_state(s));
+  }
 }
 
-Status fp64_finish(const OperatorData& od, SolveWork& sw, hipStream_t s, wf_solve_info* info) {
-  WF_TRY(solve_finish(od, sw, 1, false, s));
+Status step_finish(const OperatorData& od, SolveWork& sw, bool mixed, hipStream_t s,
+                   wf_solve_info* info) {
+  WF_TRY(sw.pull_state(s));
+  if (mixed && !sw.st_host[0].done) {
+    // stopped between reliable updates: fold the FP32 correction and take the
+    // FP64 residual, as an update would (the solve may find itself converged)
+    WF_HIP(launch_state_request_update(sw.state.as<CgState>(), s));
+    WF_TRY(solve_update(od, sw, 1, s));
+    WF_TRY(sw.pull_state(s));
+  }
+  const bool stopped = sw.st_host[0].done != 0;
+  WF_TRY(solve_finish(od, sw, 1, mixed, s));
   WF_TRY(sw.pull_state(s));
   const CgState& c = sw.st_host[0];
-  solve_infos(sw.st_host, 1, false, sw.split, od.g, 0.0, info);
-  info->status = c.done ? map_cg_status(c.status) : WF_ENOTCONV;
+  solve_infos(sw.st_host, 1, mixed, sw.split, od.g, 0.0, info);
+  info->status = stopped ? map_cg_status(c.status) : WF_ENOTCONV;
   if (info->status != WF_OK)
     return fail((wf_status)info->status, wf_status_str((wf_status)info->status));
   return {};
@@ -364,37 +398,50 @@ namespace {
 struct SnapHeader {
   uint64_t magic;
   int32_t n;
-  int32_t split;  // 1: prior-split solve (x, r, p are half spectra)
+  int32_t split;  // 1: prior-split solve (the vectors are half spectra)
   double box;
+  int32_t mixed;  // 1: mixed precision (FP64 x, r; FP32 x, r, p)
+  int32_t pad;
 };
-constexpr uint64_t SNAP_MAGIC = 0x5746534e41503031ull;  // "WFSNAP01"
+constexpr uint64_t SNAP_MAGIC = 0x5746534e41503032ull;  // "WFSNAP02"
 }  // namespace
 
 static size_t vector_len(const Grid& g, bool split) {
   return split ? 2 * (size_t)g.spec_total : (size_t)g.m;
 }
 
-size_t snapshot_bytes(const Grid& g, bool split) {
-  return sizeof(SnapHeader) + sizeof(CgState) + 3 * vector_len(g, split) * 8;
+size_t snapshot_bytes(const Grid& g, bool split, bool mixed) {
+  const size_t v = vector_len(g, split);
+  return sizeof(SnapHeader) + sizeof(CgState) + (mixed ? 2 * v * 8 + 3 * v * 4 : 3 * v * 8);
 }
 
-bool snapshot_split(const void* buf) {
+bool snapshot_kind(const void* buf, bool* split, bool* mixed) {
   SnapHeader h;
   std::memcpy(&h, buf, sizeof h);
-  return h.magic == SNAP_MAGIC && h.split == 1;
+  if (h.magic != SNAP_MAGIC) return false;
+  *split = h.split == 1;
+  *mixed = h.mixed == 1;
+  return true;
 }
 
-Status snapshot_save(const Grid& g, SolveWork& sw, void* buf, hipStream_t s) {
+// the device vectors of a snapshot, in order, and their element sizes
+static std::vector<std::pair<DevBuf*, size_t>> snap_vectors(SolveWork& sw, bool mixed) {
+  if (mixed) return {{&sw.x64, 8}, {&sw.r64, 8}, {&sw.x32, 4}, {&sw.r32, 4}, {&sw.p32, 4}};
+  return {{&sw.x64, 8}, {&sw.r64, 8}, {&sw.p64, 8}};
+}
+
+Status snapshot_save(const Grid& g, SolveWork& sw, bool mixed, void* buf, hipStream_t s) {
   char* p = static_cast<char*>(buf);
-  SnapHeader h{SNAP_MAGIC, g.n, sw.split ? 1 : 0, g.box};
+  SnapHeader h{SNAP_MAGIC, g.n, sw.split ? 1 : 0, g.box, mixed ? 1 : 0, 0};
   std::memcpy(p, &h, sizeof h);
   p += sizeof h;
   WF_HIP(hipMemcpyAsync(p, sw.state.p, sizeof(CgState), hipMemcpyDeviceToHost, s));
   p += sizeof(CgState);
-  const size_t vb = vector_len(g, sw.split) * 8;
-  WF_HIP(hipMemcpyAsync(p, sw.x64.p, vb, hipMemcpyDeviceToHost, s));
-  WF_HIP(hipMemcpyAsync(p + vb, sw.r64.p, vb, hipMemcpyDeviceToHost, s));
-  WF_HIP(hipMemcpyAsync(p + 2 * vb, sw.p64.p, vb, hipMemcpyDeviceToHost, s));
+  const size_t v = vector_len(g, sw.split);
+  for (auto& [b, es] : snap_vectors(sw, mixed)) {
+    WF_HIP(hipMemcpyAsync(p, b->p, v * es, hipMemcpyDeviceToHost, s));
+    p += v * es;
+  }
   WF_HIP(hipStreamSynchronize(s));
   return {};
 }
@@ -404,20 +451,28 @@ Status snapshot_load(const OperatorData& od, const Allocator& al, SolveWork& sw,
   const char* p = static_cast<const char*>(buf);
   SnapHeader h;
   std::memcpy(&h, p, sizeof h);
-  if (h.magic != SNAP_MAGIC || h.n != od.g.n || h.box != od.g.box || (h.split != 0 && h.split != 1))
+  if (h.magic != SNAP_MAGIC || h.n != od.g.n || h.box != od.g.box || (h.split != 0 && h.split != 1) ||
+      (h.mixed != 0 && h.mixed != 1))
     return fail(WF_EINVAL, "snapshot does not match this grid");
-  if (h.split && !od.fac_ready) return fail(WF_ESTATE, "prior-split factor not built");
-  WF_TRY(sw.ensure(al, od.g, 1, true, false, h.split == 1));
+  const bool split = h.split == 1, mixed = h.mixed == 1;
+  if (split && !od.fac_ready) return fail(WF_ESTATE, "prior-split factor not built");
+  WF_TRY(sw.ensure(al, od.g, 1, !mixed, mixed, split));
   p += sizeof h;
   CgState st;
   std::memcpy(&st, p, sizeof st);
   st.ticket = 0;
   WF_HIP(hipMemcpyAsync(sw.state.p, &st, sizeof st, hipMemcpyHostToDevice, s));
   p += sizeof(CgState);
-  const size_t vb = vector_len(od.g, h.split == 1) * 8;
-  WF_HIP(hipMemcpyAsync(sw.x64.p, p, vb, hipMemcpyHostToDevice, s));
-  WF_HIP(hipMemcpyAsync(sw.r64.p, p + vb, vb, hipMemcpyHostToDevice, s));
-  WF_HIP(hipMemcpyAsync(sw.p64.p, p + 2 * vb, vb, hipMemcpyHostToDevice, s));
+  const size_t v = vector_len(od.g, split);
+  for (auto& [b, es] : snap_vectors(sw, mixed)) {
+    WF_HIP(hipMemcpyAsync(b->p, p, v * es, hipMemcpyHostToDevice, s));
+    p += v * es;
+  }
+  // the prior-split right-hand side C b of the reliable updates, recomputed
+  // from the context's data vector (the same bits as at the start)
+  if (split && mixed)
+    WF_TRY(split_rhs(od, sw.b64.as<double>(), sw.spec64.as<double2>(), sw.bh64.as<double>(), 1,
+                     s));
   WF_HIP(hipStreamSynchronize(s));
   return {};
 }

@@ -210,3 +210,51 @@ def test_repeat_solves_bitwise_identical(ctx, pl32):
     a, _ = ctx.solve(precision="mixed", tol=1e-9, max_iter=5000)
     b, _ = ctx.solve(precision="mixed", tol=1e-9, max_iter=5000)
     assert np.array_equal(a, b)
+
+
+def test_mixed_snapshot_resume_bit_identical(pl32):
+    """A mixed-precision solve stepped, snapshotted (FP64 x, r; FP32 x, r, p;
+    scalars) and resumed in a new context continues bit for bit, and equals an
+    uninterrupted mixed solve of as many FP32 iterations."""
+    a = context()
+    _load(a, pl32)
+    a.solve_begin(precision="mixed", tol=1e-12, max_iter=100000)
+    a.solve_step(45)
+    snap = a.snapshot()
+    a.solve_step(75)
+    x_direct, info_d = a.solve_finish(allow=(WF_OK, WF_ENOTCONV))
+    assert info_d.iters_total == 120 and info_d.outer_steps >= 2
+    b = context()
+    _load(b, pl32)
+    b.resume(snap)
+    b.solve_step(75)
+    x_resumed, info_r = b.solve_finish(allow=(WF_OK, WF_ENOTCONV))
+    assert np.array_equal(x_direct, x_resumed)
+    assert info_r.outer_steps == info_d.outer_steps
+    x120, info_u = a.solve(precision="mixed", tol=1e-12, max_iter=120, allow=(WF_ENOTCONV,))
+    assert info_u.iters_total == 120
+    assert np.array_equal(x120, x_direct)
+    # the mixed snapshot holds two FP64 and three FP32 vectors
+    a.solve_begin(precision="fp64", tol=1e-12, max_iter=100)
+    a.solve_step(2)
+    assert a.snapshot().size > snap.size
+    a.close()
+    b.close()
+
+
+def test_mixed_solve_reports_stagnation(pl32):
+    """A mixed solve asked for a residual below what FP32 iterations with FP64
+    updates reach stops as stagnated (WF_ENOTCONV) instead of running to
+    max_iter, and its result is as good as the arithmetic allows."""
+    ctx = context()
+    _load(ctx, pl32)
+    x, info = ctx.solve(precision="mixed", tol=1e-17, max_iter=100000, allow=(WF_ENOTCONV,))
+    print(f"tol 1e-17: {info.iters_total} iterations, {info.outer_steps} updates, "
+          f"residual {info.rel_res_true:.2e}, stagnated {info.stagnated}")
+    assert info.status == WF_ENOTCONV and info.stagnated == 1
+    assert info.iters_total < 20000
+    assert info.rel_res_true < 1e-13
+    assert rel_l2(x, pl32["x_ref"]) < 1e-9
+    _, ok = ctx.solve(precision="mixed", tol=1e-10, max_iter=100000)
+    assert ok.status == WF_OK and ok.stagnated == 0
+    ctx.close()

@@ -192,8 +192,11 @@ def test_split_option_checks(ctx, bbks48):
     L = wf.lib()
     out = np.empty((48,) * 3)
     assert L.wf_solve(ctx._h, ctypes.byref(o), out.ctypes.data, 0, None) == WF_EINVAL
+    o = wf.opts(precision="mixed", tol=1e-8, precond="prior")
+    o.err_tol = float("nan")
+    assert L.wf_solve(ctx._h, ctypes.byref(o), out.ctypes.data, 0, None) == WF_EINVAL
     with pytest.raises(wf.WienerError):
-        ctx.solve_begin(precision="mixed", precond="prior", tol=1e-8)
+        ctx.solve_begin(precision="mixed", precond="prior", tol=-1.0)
 
 
 @pytest.mark.parametrize("n", [8, 12, 16, 24, 64, 96])
@@ -247,5 +250,30 @@ def test_split_snapshot_resume_bit_identical(bbks48):
     a.solve_begin(precision="fp64", tol=1e-12, max_iter=5000)
     a.solve_step(5)
     assert a.snapshot().size < snap.size
+    a.close()
+    b.close()
+
+
+def test_split_mixed_snapshot_resume_bit_identical(bbks48):
+    """The same for a mixed prior-split solve, whose snapshot holds half
+    spectra and whose resumed updates recompute C b from the data."""
+    d = bbks48
+    a = context()
+    _load(a, d)
+    a.solve_begin(precision="mixed", precond="prior", tol=1e-12, max_iter=100000)
+    a.solve_step(30)
+    snap = a.snapshot()
+    a.solve_step(50)
+    x_direct, info_d = a.solve_finish(allow=(WF_OK, WF_ENOTCONV))
+    assert info_d.iters_total == 80
+    b = context()
+    _load(b, d)
+    b.resume(snap)
+    b.solve_step(50)
+    x_resumed, _ = b.solve_finish(allow=(WF_OK, WF_ENOTCONV))
+    assert np.array_equal(x_direct, x_resumed)
+    x80, _ = a.solve(precision="mixed", precond="prior", tol=1e-12, max_iter=80,
+                     allow=(WF_ENOTCONV,))
+    assert np.array_equal(x80, x_direct)
     a.close()
     b.close()
