@@ -157,9 +157,10 @@ typedef struct {
   double latency_ms;          /* server: submit -> result ready on the host;
                                  0 elsewhere                                  */
   int32_t stagnated;          /* MIXED: 1 if the solve stopped (WF_ENOTCONV)
-                                 because its FP64 residual fell by less than a
-                                 factor 2 at 3 reliable updates in a row: tol
-                                 is below what the arithmetic reaches        */
+                                 because 4 reliable updates in a row did not
+                                 bring its FP64 residual 10 % below the best
+                                 so far: tol is below what the arithmetic
+                                 reaches                                      */
 } wf_solve_info;
 
 /* ---- library ----------------------------------------------------------- */

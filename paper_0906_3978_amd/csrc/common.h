@@ -62,16 +62,19 @@ struct CgState {
   double err_tol;
   int32_t hold;      // updates so far, this one included, whose residual met tol
   int32_t hold_need; // intervals the change is summed over: a residual drop of 10 at delta
-  double move_acc;   // sum of the changes of the updates after the first with the residual met
-  double prev_rel;   // FP64 relative residual at the previous reliable update
-  int32_t stall;     // consecutive updates whose FP64 residual fell by less than 2
+  double move_acc;   // sum of the changes of the updates in the current window
+  double best_rel;   // smallest FP64 relative residual of the reliable updates so far
+  int32_t stall;     // consecutive updates that did not improve on best_rel by 10 %
   int32_t stagnated; // 1: stopped because the FP64 residual no longer falls
+  int32_t upd_iter;  // iteration count at the last reliable update
+  int32_t win;       // updates summed into move_acc in the current window
 };
 
-// Reliable updates in a row whose FP64 residual fell by less than a factor 2
-// (while the FP32 one fell by 1/delta) after which a mixed solve stops as
-// stagnated: its tolerance is below what the arithmetic can reach.
-constexpr int32_t STALL_UPDATES = 3;
+// Reliable updates in a row that do not bring the FP64 residual 10 % below
+// its best so far (while the FP32 one fell by 1/delta each time) after which
+// a mixed solve stops as stagnated: its tolerance is below what the
+// arithmetic can reach.
+constexpr int32_t STALL_UPDATES = 4;
 
 // Reliable-update intervals that together reduce the recursive residual by
 // at least 10 (each reduces it by delta).

@@ -868,9 +868,14 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partials, int np
     if (st->reliable) {
       // the recursive residual decides when to refresh it in FP64; only the
       // FP64 residual decides convergence
-      // (while holding for the solution to settle only the drop by delta triggers)
+      // (while holding for the solution to settle only the drop by delta
+      // triggers); an interval longer than three times the mean so far ends
+      // too, so that a solve at its attainable accuracy, whose FP32 residual
+      // hardly falls any more, reaches its stagnation test
+      const int32_t mean = st->updates > 0 ? st->upd_iter / st->updates : 0;
+      const bool long_interval = st->updates > 0 && st->iter - st->upd_iter > 3 * mean + 10;
       if (sqrt(rho_new) <= st->delta * st->rmax || (rel <= st->tol && !st->hold) ||
-          st->iter >= st->max_iter) {
+          st->iter >= st->max_iter || long_interval) {
         st->done = 1;
         st->status = CG_UPDATE;
       }

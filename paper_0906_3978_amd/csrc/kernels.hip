@@ -375,23 +375,37 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const dou
     const double tot = reduce_partials(parts, gridDim.x, red);
     if (threadIdx.x == 0) {
       st->updates += 1;
+      st->upd_iter = st->iter;
       st->pending = 0;  // folded
       const double rel = sqrt(st->outer_rr) / st->bnorm;
-      // with err_tol: once the residual meets tol, the solve goes on until the
-      // updates after that one have reduced the residual by 10 (hold_need of
-      // them) and changed the solution by at most err_tol in all: that change
-      // shows the error the residual had hidden
+      // with err_tol: once the residual meets tol, the solve goes on in
+      // windows of the updates that reduce the residual by 10 (hold_need of
+      // them) and stops after the first window whose summed changes of the
+      // solution are at most err_tol: that change shows the error the
+      // residual had hidden
       if (rel <= st->tol) {
-        if (st->hold > 0) st->move_acc += st->move;
+        if (st->hold > 0) {
+          st->move_acc += st->move;
+          st->win += 1;
+        }
         st->hold += 1;
       } else {
         st->hold = 0;
+        st->win = 0;
         st->move_acc = 0.0;
       }
-      const bool settled = !(st->err_tol > 0.0) ||
-                           (st->hold > st->hold_need && st->move_acc <= st->err_tol);
-      st->stall = (st->updates > 1 && !(rel < 0.5 * st->prev_rel)) ? st->stall + 1 : 0;
-      st->prev_rel = rel;
+      const bool window = st->win >= st->hold_need;
+      const bool settled = !(st->err_tol > 0.0) || (window && st->move_acc <= st->err_tol);
+      if (window && !settled) {  // the next window starts
+        st->win = 0;
+        st->move_acc = 0.0;
+      }
+      if (st->updates > 1 && !(rel < 0.9 * st->best_rel)) {
+        st->stall += 1;
+      } else {
+        st->stall = 0;
+      }
+      if (st->updates == 1 || rel < st->best_rel) st->best_rel = rel;
       if (rel <= st->tol && settled) {
         st->status = CG_CONVERGED;
       } else if (st->iter >= st->max_iter) {

@@ -234,10 +234,12 @@ def test_mixed_snapshot_resume_bit_identical(pl32):
     x120, info_u = a.solve(precision="mixed", tol=1e-12, max_iter=120, allow=(WF_ENOTCONV,))
     assert info_u.iters_total == 120
     assert np.array_equal(x120, x_direct)
-    # the mixed snapshot holds two FP64 and three FP32 vectors
+    # the mixed snapshot holds two FP64 and three FP32 vectors (28 bytes per
+    # cell), the FP64 one three FP64 vectors (24)
     a.solve_begin(precision="fp64", tol=1e-12, max_iter=100)
     a.solve_step(2)
-    assert a.snapshot().size > snap.size
+    s64 = a.snapshot().size
+    assert snap.size - s64 == 4 * 32 ** 3
     a.close()
     b.close()
 
@@ -252,7 +254,7 @@ def test_mixed_solve_reports_stagnation(pl32):
     print(f"tol 1e-17: {info.iters_total} iterations, {info.outer_steps} updates, "
           f"residual {info.rel_res_true:.2e}, stagnated {info.stagnated}")
     assert info.status == WF_ENOTCONV and info.stagnated == 1
-    assert info.iters_total < 20000
+    assert info.iters_total < 5000
     assert info.rel_res_true < 1e-13
     assert rel_l2(x, pl32["x_ref"]) < 1e-9
     _, ok = ctx.solve(precision="mixed", tol=1e-10, max_iter=100000)
