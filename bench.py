@@ -136,7 +136,9 @@ def _iteration_roofline(prof, keys, n):
 
 PLAIN_F64 = ["zfwd_f64", "yfwd_f64", "xlam_f64", "yinv_f64", "zinv_f64", "update_f64"]
 PLAIN_F32 = ["zfwd_f32", "yfwd_f32", "xlam_f32", "yinv_f32", "zinv_f32", "update_f32"]
-SPLIT_F32 = ["sxinv_f32", "yinv_f32", "szw_f32", "yfwd_f32", "sxfwd_f32", "update_f32"]
+# the FP32 prior-split iteration applies r -= alpha q in its first pass (no
+# update kernel)
+SPLIT_F32 = ["sxinv_f32", "yinv_f32", "szw_f32", "yfwd_f32", "sxfwd_f32"]
 
 
 def _dominant(prof, keys):
@@ -407,6 +409,7 @@ def batch_run(nrhs, tol, precond="prior"):
     if it:
         it["bytes_per_cell_per_rhs"] = round(it["bytes"] / (nrhs * wl.n ** 3), 2)
         it["model_ms_survey"] = round(76.25 * nrhs * wl.n ** 3 / (HBM_PEAK_GBS * 1e9) * 1e3, 3)
+        it["model_ms_fold"] = round(72.0 * nrhs * wl.n ** 3 / (HBM_PEAK_GBS * 1e9) * 1e3, 3)
     t = time.perf_counter()
     singles = []
     one = torch.empty((wl.n,) * 3, dtype=torch.float64, device=dev)
@@ -576,6 +579,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="live kernel timing over the timed steps: bracket one launch in this "
+                         "many of each kernel class with events (1: every launch)")
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling run: one deposit, this many mixed iterations (of --precond) "
                          "and a 1 GiB device copy (the reference for scaling HBM counters), "
@@ -649,7 +655,7 @@ def main():
             f"outer={info.outer_steps} rel_res_true={info.rel_res_true:.2e}")
 
     if not args.no_profile:
-        ctx.profile_enable(True)
+        ctx.profile_enable(True, every=args.profile_every)
     torch.cuda.synchronize()
     lat = []
     infos = []
@@ -694,11 +700,8 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                     "traffic": traffic_for(dom, bpl), "algorithmic_bytes_per_launch": bpl,
                     "avg_launch_us": round(avg_s * 1e6, 2)}
-        # whole-iteration figure: the sweeps + update of the FP32 inner CG
-        if args.precond == "prior":
-            it_keys = ["sxinv_f32", "yinv_f32", "szw_f32", "yfwd_f32", "sxfwd_f32", "update_f32"]
-        else:
-            it_keys = ["zfwd_f32", "yfwd_f32", "xlam_f32", "yinv_f32", "zinv_f32", "update_f32"]
+        # whole-iteration figure: the sweeps (+ update) of the FP32 inner CG
+        it_keys = SPLIT_F32 if args.precond == "prior" else PLAIN_F32
         if all(k in prof for k in it_keys):
             it_ms = sum(prof[k]["ms"] / prof[k]["launches"] for k in it_keys)
             it_b = sum(prof[k]["bytes"] / prof[k]["launches"] for k in it_keys)

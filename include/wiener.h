@@ -238,7 +238,8 @@ wf_status wf_solve(wf_ctx* ctx, const wf_solve_opts* opts, double* s_out,
  * wf_snapshot_bytes() bytes (the size for the active solve; without one, that
  * of a plain FP64 solve): the scalars and x, r, p in FP64, or for a mixed
  * solve the FP64 x and r and the FP32 x, r, p -- half spectra for the
- * prior-split form.  wf_solve_resume restores it into a context with the same
+ * prior-split form, whose FP32 iteration ends with its step pending until the
+ * next iteration applies it and so also keeps q.  wf_solve_resume restores it into a context with the same
  * grid, mask, power and rhs (the snapshot records its form), and
  * wf_solve_finish writes s and info (a mixed solve stopped between reliable
  * updates first folds its FP32 correction and takes the FP64 residual, as an
@@ -384,11 +385,14 @@ typedef enum {
   WF_PROF_SDIR_F64, WF_PROF_SXINV_F64, WF_PROF_SZW_F64, WF_PROF_SXFWD_F64
 } wf_prof_kind;
 
-/* Per class: active launches, summed device time (HIP events recorded on the
- * context's stream around every launch) and algorithmic HBM bytes (the bytes
- * the pass must read and write once: inputs, outputs, the half spectrum).
- * Launches that found their solve already stopped (shorter than a quarter of
- * the class's median) are counted in `skipped` and left out of the totals. */
+/* Per class: full-work launches, their summed device time (HIP events that
+ * the runtime stamps with each timed dispatch's start and end) and their
+ * algorithmic HBM bytes (the bytes the pass must read and write once:
+ * inputs, outputs, the half spectrum).  Launches that did less than the
+ * class's full work (right-hand sides already stopped, or the first
+ * direction of a CG cycle, which reads fewer vectors) run shorter than 0.8 of
+ * the class's median: they are counted in `skipped` and left out of the
+ * totals, whose bytes assume the full work. */
 typedef struct {
   int64_t launches[WF_PROF_KINDS];
   int64_t skipped[WF_PROF_KINDS];
@@ -396,7 +400,10 @@ typedef struct {
   double bytes[WF_PROF_KINDS];
 } wf_profile;
 
-/* Turns event timing on (1) or off (0) and clears the counters. */
+/* Turns event timing off (0) or on and clears the counters: on = 1 times
+   every launch, on = k > 1 one launch in k of each kernel class (the rest
+   run without events, which keeps the timing's own cost off the work it
+   measures).  Negative values are rejected with WF_EINVAL. */
 wf_status wf_profile_enable(wf_ctx* ctx, int32_t on);
 /* Synchronises the stream and returns the counters since enabling. */
 wf_status wf_profile_read(wf_ctx* ctx, wf_profile* out);

@@ -467,8 +467,13 @@ class Context:
         self._check(self._L.wf_solve_finish(self._h, out.ctypes.data, WF_HOST, C.byref(si)), ok=allow)
         return out, _info(si)
 
-    def profile_enable(self, on=True):
-        self._check(self._L.wf_profile_enable(self._h, 1 if on else 0))
+    def profile_enable(self, on=True, every=1):
+        """Event timing on or off; with every > 1 one launch in `every` of
+        each kernel class is timed."""
+        every = int(every)
+        if every < 1:
+            raise ValueError("every must be >= 1")
+        self._check(self._L.wf_profile_enable(self._h, every if on else 0))
 
     def profile_read(self):
         pr = Profile()

@@ -837,12 +837,14 @@ wf_status wf_inverse_weighting(wf_ctx* c, wf_scheme scheme, int32_t ss, double* 
 
 wf_status wf_profile_enable(wf_ctx* c, int32_t on) {
   if (!c) return WF_EINVAL;
+  if (on < 0) return finish(c, fail(WF_EINVAL, "profile_enable: negative sampling period"));
   Status s = set_device(c);
   if (!s.ok()) return finish(c, s);
   (void)hipStreamSynchronize(c->stream);
   c->prof.harvest();
   c->prof.clear();
   c->prof.on = on != 0;
+  c->prof.every = on > 1 ? on : 1;
   c->od.prof = c->prof.on ? &c->prof : nullptr;
   return WF_OK;
 }

@@ -53,6 +53,7 @@ void Profiler::clear() {
   for (int k = 0; k < WF_PROF_KINDS; ++k) {
     dur[k].clear();
     byt[k].clear();
+    seen[k] = 0;
   }
 }
 
@@ -63,7 +64,7 @@ void Profiler::totals(int64_t* launches, int64_t* skipped, double* ms, double* b
     if (dur[k].empty()) continue;
     std::vector<float> t = dur[k];
     std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
-    const float cut = 0.25f * t[t.size() / 2];
+    const float cut = 0.8f * t[t.size() / 2];
     for (size_t i = 0; i < dur[k].size(); ++i) {
       if (dur[k][i] < cut) {
         skipped[k] += 1;
@@ -76,8 +77,14 @@ void Profiler::totals(int64_t* launches, int64_t* skipped, double* ms, double* b
   }
 }
 
-int Profiler::begin(int kind, double b, hipStream_t s) {
+TimedLaunch& timed_launch() {
+  static thread_local TimedLaunch t;
+  return t;
+}
+
+int Profiler::begin(int kind, double b, hipStream_t s, bool multi) {
   if (!on) return -1;
+  if (seen[kind]++ % every != 0) return -1;
   if (pending.size() >= 8192) {
     (void)hipStreamSynchronize(s);
     harvest();
@@ -87,16 +94,34 @@ int Profiler::begin(int kind, double b, hipStream_t s) {
     if (!pool.empty()) {
       x = pool.back();
       pool.pop_back();
-    } else if (hipEventCreate(&x) != hipSuccess) {
+    } else if (hipEventCreateWithFlags(&x, hipEventDisableSystemFence) != hipSuccess) {
       return -1;
     }
   }
-  (void)hipEventRecord(e[0], s);
+  if (multi) {
+    (void)hipEventRecord(e[0], s);
+  } else {
+    TimedLaunch& t = timed_launch();
+    t.start = e[0];
+    t.stop = e[1];
+  }
   pending.push_back(Pair{e[0], e[1], kind, b});
   return (int)pending.size() - 1;
 }
 
-void Profiler::end(int idx, hipStream_t s) { (void)hipEventRecord(pending[idx].b, s); }
+void Profiler::end(int idx, hipStream_t s, bool multi) {
+  if (multi) {
+    (void)hipEventRecord(pending[idx].b, s);
+    return;
+  }
+  TimedLaunch& t = timed_launch();
+  if (t.start == pending[idx].a) {  // nothing was launched (an early error return)
+    t.start = t.stop = nullptr;
+    pool.push_back(pending[idx].a);
+    pool.push_back(pending[idx].b);
+    pending.erase(pending.begin() + idx);
+  }
+}
 
 void Profiler::harvest() {
   for (auto& pr : pending) {
@@ -535,7 +560,25 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
   const double vb = (double)sizeof(T) * g.m * nrhs;
   const double sb = 2.0 * sizeof(T) * g.spec_total * nrhs;
   const cplx<T>* pc = reinterpret_cast<const cplx<T>*>(pin);
-  if (rdir) {
+  if (rdir && mode == SM_FWD_CGQF) {
+    // folded CG: r, q, p, x in; r, p, x and the x-transformed work spectrum
+    // out; then the new r.r
+    StrArgs<T> xa = split_x_args<T>(od, reinterpret_cast<const cplx<T>*>(rdir), work, nullptr,
+                                    nullptr, st, skip, partials);
+    xa.s0.p = const_cast<cplx<T>*>(pc);
+    xa.s1.p = xa.s0.p + g.spec_main;
+    xa.s0.x = reinterpret_cast<cplx<T>*>(xdir);
+    xa.s1.x = xa.s0.x + g.spec_main;
+    xa.s0.r = const_cast<cplx<T>*>(reinterpret_cast<const cplx<T>*>(rdir));
+    xa.s1.r = xa.s0.r + g.spec_main;
+    xa.s0.q = reinterpret_cast<const cplx<T>*>(out);
+    xa.s1.q = xa.s0.q + g.spec_main;
+    {
+      ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 8 * sb, s);
+      WF_HIP(launch_strided<T>(g.n, SM_INV_FOLD, xa, nrhs, s));
+    }
+    WF_HIP(launch_finalize(FIN_RRF, partials, xa.nblk0 + xa.nblk1, skip, st, nrhs, s));
+  } else if (rdir) {
     // CG: r, p, x in; p, x and the x-transformed work spectrum out
     ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 6 * sb, s);
     StrArgs<T> xa = split_x_args<T>(od, reinterpret_cast<const cplx<T>*>(rdir), work, nullptr,
@@ -582,13 +625,14 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
   {
     // work spectrum in, result out; CGQ also reads p, RES y and b (FP64)
     double xb = 2 * sb;
-    if (mode == SM_FWD_CGQ) xb += sb;
+    if (mode == SM_FWD_CGQ || mode == SM_FWD_CGQF) xb += sb;
     if (mode == SM_FWD_RES) xb += 2 * sb;
     ProfScope ps(od.prof, f64 ? WF_PROF_SXFWD_F64 : WF_PROF_SXFWD_F32, xb, s);
     WF_HIP(launch_strided<T>(g.n, mode, xa, nrhs, s));
   }
-  if (mode == SM_FWD_CGQ || mode == SM_FWD_RES)
-    WF_HIP(launch_finalize(mode == SM_FWD_CGQ ? FIN_PQ : FIN_RES, partials, xa.nblk0 + xa.nblk1,
+  if (mode == SM_FWD_CGQ || mode == SM_FWD_RES || mode == SM_FWD_CGQF)
+    WF_HIP(launch_finalize(mode == SM_FWD_CGQ ? FIN_PQ : mode == SM_FWD_CGQF ? FIN_PQF : FIN_RES,
+                           partials, xa.nblk0 + xa.nblk1,
                            skip, st, nrhs, s));
   return {};
 }
@@ -681,7 +725,7 @@ Status run_deposit(const Allocator& al, const OperatorData& od, DepositWork& dw,
   const double c = (double)nf / g.box;
   {
     const int st = scheme == WF_NGP ? 1 : (scheme == WF_CIC ? 8 : 27);
-    ProfScope ps(od.prof, WF_PROF_DEPOSIT, 8.0 * mf + 24.0 * ngal + 16.0 * st * ngal, s);
+    ProfScope ps(od.prof, WF_PROF_DEPOSIT, 8.0 * mf + 24.0 * ngal + 16.0 * st * ngal, s, true);
     WF_HIP(launch_fill_i64(grid, mf, s));
     WF_HIP(launch_deposit(scheme, xyz, ngal, c, nf, grid, s));
   }
@@ -705,7 +749,7 @@ Status run_lowpass(const Allocator& al, const OperatorData& od, DepositWork& dw,
   ProfScope pss(od.prof, WF_PROF_SUPERSAMPLE,
                 8.0 * mf + 2 * 16.0 * nf * nf * h + 2 * 16.0 * nf * n * h + 16.0 * g.spec_total * 5 +
                     8.0 * g.m,
-                s);
+                s, true);
   if (dw.tw_fine_n != nf) {
     WF_TRY(make_twiddles(al, nf, dw.tw_fine, nullptr, s));
     dw.tw_fine_n = nf;
@@ -785,11 +829,16 @@ Status run_lowpass(const Allocator& al, const OperatorData& od, DepositWork& dw,
   return {};
 }
 
-// Bytes per cell of one CG iteration, FP32 (FP64 doubles it).  Both forms
-// come to 76: in the split form a half spectrum is 4 B per cell and the passes
-// move x inverse with the direction update 24 (r, p, x in; p, x, work out),
-// y 8, z middle 12, y 8, x forward with q 12, r update 12.
-double model_bytes_iteration(bool fp64, bool /*split*/) { return fp64 ? 152.0 : 76.0; }
+// Bytes per cell of one CG iteration.  Plain form, FP32: 76 (FP64 doubles
+// it).  Split form, FP64: 152, a half spectrum being 8 B per cell: x inverse
+// with the direction update 48 (r, p, x in; p, x, work out), y 16, z middle
+// 24, y 16, x forward with q 24, r update 24.  Split form, FP32 (the folded
+// iteration): 72 -- x inverse with the r update and the direction 32 (r, q, p,
+// x in; r, p, x, work out), y 8, z middle 12, y 8, x forward with q 12.
+double model_bytes_iteration(bool fp64, bool split) {
+  if (fp64) return 152.0;
+  return split ? 72.0 : 76.0;
+}
 // FP64 residual b - A x, also 104 in both forms (split: x inverse 16, y 16,
 // z middle 24, y 16, x forward with y and b in 32)
 double model_bytes_residual(bool /*split*/) { return 104.0; }

@@ -494,12 +494,13 @@ template <typename T, int N> __device__ __forceinline__ T sqrt_d(int kz) {
 // (f: factor, pv: aux value, bv: b value).
 template <typename T, int N, int MODE>
 __device__ __forceinline__ cplx<T> split_out(T f, int kz, bool dc, cplx<T> v, cplx<T> pv,
-                                            cplx<double> bv, double& acc) {
+                                            cplx<double> bv, double& acc, double& acc2) {
   f *= sqrt_d<T, N>(kz);
   cplx<T> o = {f * v.x, f * v.y};
-  if constexpr (MODE == SM_FWD_CGQ) {
+  if constexpr (MODE == SM_FWD_CGQ || MODE == SM_FWD_CGQF) {
     if (!dc) o = cadd(o, pv);
     acc += (double)pv.x * (double)o.x + (double)pv.y * (double)o.y;
+    if constexpr (MODE == SM_FWD_CGQF) acc2 += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
   } else if constexpr (MODE == SM_FWD_RES) {
     if (!dc) o = cadd(o, pv);
     o = {(T)(bv.x - (double)o.x), (T)(bv.y - (double)o.y)};
@@ -508,13 +509,18 @@ __device__ __forceinline__ cplx<T> split_out(T f, int kz, bool dc, cplx<T> v, cp
   return o;
 }
 
+// Waves per SIMD a strided block must allow: its LDS tile (up to 64 KB) fits
+// twice per CU, so 1024-thread blocks are held to 64 VGPRs to run two at once.
+template <int NTS> constexpr int strided_waves() { return NTS >= 1024 ? 8 : 1; }
+
 template <typename T, int N, int MODE, int TB, int NTS>
-__global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
+__global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T> a) {
   constexpr int NT = NTS;
   // nontemporal in the x pass only
   constexpr bool NTA = MODE == SM_FWD_LAM_INV || MODE == SM_INV_SCALE || MODE == SM_INV_DIR ||
-                       MODE == SM_FWD_SCALE || MODE == SM_FWD_CGQ || MODE == SM_FWD_RES;
-  constexpr bool SCALE_IN = MODE == SM_INV_SCALE || MODE == SM_INV_DIR;
+                       MODE == SM_FWD_SCALE || MODE == SM_FWD_CGQ || MODE == SM_FWD_RES ||
+                       MODE == SM_INV_FOLD || MODE == SM_FWD_CGQF;
+  constexpr bool SCALE_IN = MODE == SM_INV_SCALE || MODE == SM_INV_DIR || MODE == SM_INV_FOLD;
   using V = cplx<T>;
   using R = vec16<T>;
   constexpr int CW = 16 / sizeof(V);
@@ -524,9 +530,10 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   constexpr int PER = (ITEMS + NT - 1) / NT;
   __shared__ __align__(16) V lds[TB * N];
   __shared__ V twl[N];
-  constexpr bool SPLIT_OUT = MODE == SM_FWD_SCALE || MODE == SM_FWD_CGQ || MODE == SM_FWD_RES;
-  constexpr bool REDUCE = MODE == SM_FWD_CGQ || MODE == SM_FWD_RES;
-  __shared__ double red[REDUCE ? NT / 64 : 1];
+  constexpr bool SPLIT_OUT = MODE == SM_FWD_SCALE || MODE == SM_FWD_CGQ || MODE == SM_FWD_RES ||
+                             MODE == SM_FWD_CGQF;
+  constexpr bool REDUCE = MODE == SM_FWD_CGQ || MODE == SM_FWD_RES || MODE == SM_FWD_CGQF;
+  __shared__ double red[(REDUCE || MODE == SM_INV_FOLD) ? NT / 64 : 1];
   const int rhs = blockIdx.y;
   if (a.st && skip_rhs(a.st + rhs, a.skip)) return;
   const T* fac_r = a.fac + rhs * a.rhs_fac;
@@ -579,27 +586,81 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           }
         }
       }
-#pragma unroll
-      for (int c = 0; c < PER; ++c) {
+      // scaled (SCALE_IN) into the LDS tile
+      auto to_lds = [&](int c) {
         const int q = threadIdx.x + c * NT;
-        if (ITEMS % NT == 0 || q < ITEMS) {
-          if constexpr (SCALE_IN) {
-            const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-            T f[CW];
-            int kz[CW];
-            bool dc[CW];
-            split_facs<T, N, CW>(fac_r, s, outer, b0 + b, i, f, kz, dc);
+        if constexpr (SCALE_IN) {
+          const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+          T f[CW];
+          int kz[CW];
+          bool dc[CW];
+          split_facs<T, N, CW>(fac_r, s, outer, b0 + b, i, f, kz, dc);
 #pragma unroll
-            for (int j = 0; j < CW; ++j) {
-              const T g = f[j] * ((T)a.in_scale / sqrt_d<T, N>(kz[j]));
-              buf[c][2 * j] *= g;
-              buf[c][2 * j + 1] *= g;
+          for (int j = 0; j < CW; ++j) {
+            const T g = f[j] * ((T)a.in_scale / sqrt_d<T, N>(kz[j]));
+            buf[c][2 * j] *= g;
+            buf[c][2 * j + 1] *= g;
+          }
+        }
+        *reinterpret_cast<R*>(lds + q * CW) = buf[c];
+      };
+      if constexpr (MODE == SM_INV_FOLD) {
+        // folded CG step: `in` is r.  Pending (the previous iteration's
+        // alpha and beta): x += alpha p, r -= alpha q, p = r + beta p.  First
+        // direction of a cycle: p = r.  Otherwise p is ready (a reliable
+        // update continued it).  Block partial of the new r.r.
+        const CgState* cs = a.st + rhs;
+        const bool pending = cs->pending != 0, first = cs->first != 0;
+        const T alpha = (T)cs->alpha, beta = (T)cs->beta;
+        double rr = 0.0;
+        if (pending) {
+          // one element group at a time (few registers: two blocks per CU)
+#pragma unroll
+          for (int c = 0; c < PER; ++c) {
+            const int q = threadIdx.x + c * NT;
+            if (ITEMS % NT == 0 || q < ITEMS) {
+              const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+              const int64_t vo = rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i);
+              const R pv = ld16x<NTA>(reinterpret_cast<const T*>(s.p + vo));
+              const R qv = ld16x<NTA>(reinterpret_cast<const T*>(s.q + vo));
+              const R xv = ld16x<NTA>(reinterpret_cast<const T*>(s.x + vo));
+              st16x<NTA>(reinterpret_cast<T*>(s.x + vo), xv + alpha * pv);
+              const R rn = buf[c] - alpha * qv;
+              st16x<NTA>(reinterpret_cast<T*>(s.r + vo), rn);
+#pragma unroll
+              for (int j = 0; j < 2 * CW; ++j) rr += (double)rn[j] * (double)rn[j];
+              buf[c] = rn + beta * pv;
+              st16x<NTA>(reinterpret_cast<T*>(s.p + vo), buf[c]);
+              to_lds(c);
             }
           }
-          *reinterpret_cast<R*>(lds + q * CW) = buf[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < PER; ++c) {
+            const int q = threadIdx.x + c * NT;
+            if (ITEMS % NT == 0 || q < ITEMS) {
+              const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
+              const int64_t vo = rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i);
+#pragma unroll
+              for (int j = 0; j < 2 * CW; ++j) rr += (double)buf[c][j] * (double)buf[c][j];
+              T* pp = reinterpret_cast<T*>(s.p + vo);
+              if (first) st16x<NTA>(pp, buf[c]);
+              else buf[c] = ld16x<NTA>(pp);
+              to_lds(c);
+            }
+          }
+        }
+        const double part = block_sum(rr, red);
+        if (threadIdx.x == 0) a.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = part;
+      } else {
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+          const int q = threadIdx.x + c * NT;
+          if (ITEMS % NT == 0 || q < ITEMS) to_lds(c);
         }
       }
     } else {
+      double rr_nv = 0.0;  // INV_FOLD: r.r of this thread
       for (int e = threadIdx.x; e < TB * N; e += NT) {
         const int b = e % TB, i = e / TB;
         V v;
@@ -619,6 +680,24 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           }
           s.p[o] = v;
         }
+        if constexpr (MODE == SM_INV_FOLD) {
+          const CgState* cs = a.st + rhs;
+          const int64_t o = rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i);
+          if (cs->pending) {
+            const T al = (T)cs->alpha, be = (T)cs->beta;
+            const V pv = s.p[o], qv = s.q[o], xv = s.x[o];
+            s.x[o] = V{xv.x + al * pv.x, xv.y + al * pv.y};
+            v = V{v.x - al * qv.x, v.y - al * qv.y};
+            s.r[o] = v;
+            rr_nv += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            v = V{v.x + be * pv.x, v.y + be * pv.y};
+            s.p[o] = v;
+          } else {
+            rr_nv += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            if (cs->first) s.p[o] = v;
+            else v = s.p[o];
+          }
+        }
         if constexpr (SCALE_IN) {
           T f;
           int kz;
@@ -628,6 +707,10 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           v = {v.x * f, v.y * f};
         }
         lds[e] = v;
+      }
+      if constexpr (MODE == SM_INV_FOLD) {
+        const double part = block_sum(rr_nv, red);
+        if (threadIdx.x == 0) a.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = part;
       }
     }
   } else {
@@ -662,9 +745,12 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
   }
   load_twiddles<T, N, NT>(twl, a.tw);
   // split CGQ / RES: the aux vector at the output's positions, requested
-  // before the FFT so that the loads complete under it (VEC tiles)
-  R avp[(REDUCE && VEC) ? PER : 1];
-  if constexpr (REDUCE && VEC) {
+  // before the FFT so that the loads complete under it (VEC tiles of up to
+  // 512 threads; with 1024 the registers are short and other waves hide the
+  // loads, issued after the FFT)
+  constexpr bool PRELOAD = REDUCE && VEC && NT <= 512;
+  R avp[PRELOAD ? PER : 1];
+  if constexpr (PRELOAD) {
 #pragma unroll
     for (int c = 0; c < PER; ++c) {
       const int q = threadIdx.x + c * NT;
@@ -743,7 +829,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
     }
   } else if constexpr (SPLIT_OUT) {
     // x-pass segments only (the batch is contiguous)
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     const int64_t ob = rhs * s.out_rhs;
     const int ncols = s.n_btiles * TB;
     if constexpr (VEC) {
@@ -755,7 +841,11 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
           const int64_t off = ob + vec_off<N>(outer, ncols, b0 + b, i);
           const R v = *reinterpret_cast<const R*>(lds + q * CW);
           R av{};
-          if constexpr (REDUCE) av = avp[c];
+          if constexpr (PRELOAD) {
+            av = avp[c];
+          } else if constexpr (REDUCE) {
+            av = ld16x<NTA>(reinterpret_cast<const T*>(s.aux + off));
+          }
           T f[CW];
           int kz[CW];
           bool dc[CW];
@@ -766,7 +856,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
             cplx<double> bv{0.0, 0.0};
             if constexpr (MODE == SM_FWD_RES) bv = s.bvec[off + j];
             const cplx<T> r = split_out<T, N, MODE>(f[j], kz[j], dc[j], V{v[2 * j], v[2 * j + 1]},
-                                                    V{av[2 * j], av[2 * j + 1]}, bv, acc);
+                                                    V{av[2 * j], av[2 * j + 1]}, bv, acc, acc2);
             o[2 * j] = r.x;
             o[2 * j + 1] = r.y;
           }
@@ -784,10 +874,17 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
         const V pv = REDUCE ? s.aux[off] : V{T(0), T(0)};
         cplx<double> bv{0.0, 0.0};
         if constexpr (MODE == SM_FWD_RES) bv = s.bvec[off];
-        s.out[off] = split_out<T, N, MODE>(f, kz, dc, lds[e], pv, bv, acc);
+        s.out[off] = split_out<T, N, MODE>(f, kz, dc, lds[e], pv, bv, acc, acc2);
       }
     }
-    if constexpr (REDUCE) {
+    if constexpr (MODE == SM_FWD_CGQF) {
+      const double part = block_sum(acc, red);
+      const double part2 = block_sum(acc2, red);
+      if (threadIdx.x == 0) {
+        a.partials[(int64_t)rhs * 2 * gridDim.x + blockIdx.x] = part;
+        a.partials[((int64_t)rhs * 2 + 1) * gridDim.x + blockIdx.x] = part2;
+      }
+    } else if constexpr (REDUCE) {
       const double part = block_sum(acc, red);
       if (threadIdx.x == 0) a.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = part;
     }
@@ -832,14 +929,7 @@ __global__ __launch_bounds__(NTS) void k_strided(StrArgs<T> a) {
 // finalize: sum the block partials of one reduction per RHS (fixed order)
 // and update the scalar CG state
 // ---------------------------------------------------------------------------
-template <int KIND>
-__global__ __launch_bounds__(256) void k_finalize(const double* partials, int nparts, int skip,
-                                                  CgState* st_all) {
-  __shared__ double red[4];
-  const int rhs = blockIdx.x;
-  CgState* st = st_all + rhs;
-  if (skip_rhs(st, skip)) return;
-  const double* p = partials + (int64_t)rhs * nparts;
+__device__ __forceinline__ double sum_parts(const double* p, int nparts, double* red) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int i = threadIdx.x;
   for (; i + 768 < nparts; i += 1024) {
@@ -849,50 +939,99 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partials, int np
     s3 += p[i + 768];
   }
   for (; i < nparts; i += 256) s0 += p[i];
-  const double tot = block_sum((s0 + s1) + (s2 + s3), red);
-  if (threadIdx.x != 0) return;
-  if constexpr (KIND == FIN_PQ) {
-    st->pending = 0;  // the z pass of this iteration applied it
-    st->pq = tot;
-    if (!(tot > 0.0) || !isfinite(tot)) {
+  return block_sum((s0 + s1) + (s2 + s3), red);
+}
+
+// Iteration bookkeeping and stopping once the new recursive residual r.r is
+// known (thread 0).
+__device__ __forceinline__ void count_iteration(CgState* st, double rho_new) {
+  st->iter += 1;
+  const double rel = sqrt(rho_new) / st->bnorm;
+  st->rel = rel;
+  if (st->reliable) {
+    // the recursive residual decides when to refresh it in FP64; only the
+    // FP64 residual decides convergence
+    // (while holding for the solution to settle only the drop by delta
+    // triggers); an interval longer than three times the mean so far ends
+    // too, so that a solve at its attainable accuracy, whose FP32 residual
+    // hardly falls any more, reaches its stagnation test
+    const int32_t mean = st->updates > 0 ? st->upd_iter / st->updates : 0;
+    const bool long_interval = st->updates > 0 && st->iter - st->upd_iter > 3 * mean + 10;
+    if (sqrt(rho_new) <= st->delta * st->rmax || (rel <= st->tol && !st->hold) ||
+        st->iter >= st->max_iter || long_interval) {
+      st->done = 1;
+      st->status = CG_UPDATE;
+    }
+  } else if (rel <= st->tol) {
+    st->done = 1;
+    st->status = CG_CONVERGED;
+  } else if (st->iter >= st->max_iter) {
+    st->done = 1;
+    st->status = CG_MAXITER;
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_finalize(const double* partials, int nparts, int skip,
+                                                  CgState* st_all) {
+  __shared__ double red[4];
+  const int rhs = blockIdx.x;
+  CgState* st = st_all + rhs;
+  if (skip_rhs(st, skip)) return;
+  if constexpr (KIND == FIN_PQF) {
+    const double* p = partials + (int64_t)rhs * 2 * nparts;
+    const double pq = sum_parts(p, nparts, red);
+    const double qq = sum_parts(p + nparts, nparts, red);
+    if (threadIdx.x != 0) return;
+    st->pq = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) {
       st->done = 1;
       st->status = CG_BREAKDOWN;
-    } else {
-      st->alpha = st->rho / tot;
+      st->pending = 0;
+      return;
     }
-  } else if constexpr (KIND == FIN_RR) {
-    const double rho_new = tot;
-    st->iter += 1;
-    const double rel = sqrt(rho_new) / st->bnorm;
-    st->rel = rel;
-    if (st->reliable) {
-      // the recursive residual decides when to refresh it in FP64; only the
-      // FP64 residual decides convergence
-      // (while holding for the solution to settle only the drop by delta
-      // triggers); an interval longer than three times the mean so far ends
-      // too, so that a solve at its attainable accuracy, whose FP32 residual
-      // hardly falls any more, reaches its stagnation test
-      const int32_t mean = st->updates > 0 ? st->upd_iter / st->updates : 0;
-      const bool long_interval = st->updates > 0 && st->iter - st->upd_iter > 3 * mean + 10;
-      if (sqrt(rho_new) <= st->delta * st->rmax || (rel <= st->tol && !st->hold) ||
-          st->iter >= st->max_iter || long_interval) {
-        st->done = 1;
-        st->status = CG_UPDATE;
-      }
-    } else if (rel <= st->tol) {
-      st->done = 1;
-      st->status = CG_CONVERGED;
-    } else if (st->iter >= st->max_iter) {
-      st->done = 1;
-      st->status = CG_MAXITER;
-    }
-    st->beta = rho_new / st->rho;
-    st->rho_old = st->rho;
-    st->rho = rho_new;
-    st->first = 0;
+    // alpha from the exact r.r; the next r.r for beta before r itself is
+    // updated: |r - alpha q|^2 = r.r - 2 alpha r.q + alpha^2 q.q, with r.q =
+    // p.q (r and p differ by a multiple of the previous direction, which is
+    // conjugate to p), that is alpha^2 q.q - r.r.  A negative value (total
+    // cancellation) restarts the direction.
+    const double alpha = st->rho / pq;
+    const double rho_next = alpha * alpha * qq - st->rho;
+    st->alpha = alpha;
+    st->beta = rho_next > 0.0 ? rho_next / st->rho : 0.0;
     st->pending = 1;
-  } else {  // FIN_RES
-    st->outer_rr = tot;
+    return;
+  } else {
+    const double tot = sum_parts(partials + (int64_t)rhs * nparts, nparts, red);
+    if (threadIdx.x != 0) return;
+    if constexpr (KIND == FIN_PQ) {
+      st->pending = 0;  // the z pass of this iteration applied it
+      st->pq = tot;
+      if (!(tot > 0.0) || !isfinite(tot)) {
+        st->done = 1;
+        st->status = CG_BREAKDOWN;
+      } else {
+        st->alpha = st->rho / tot;
+      }
+    } else if constexpr (KIND == FIN_RR) {
+      count_iteration(st, tot);
+      st->beta = tot / st->rho;
+      st->rho_old = st->rho;
+      st->rho = tot;
+      st->first = 0;
+      st->pending = 1;
+    } else if constexpr (KIND == FIN_RRF) {
+      // after INV_FOLD: when it applied the previous step, one iteration more
+      if (st->pending) {
+        count_iteration(st, tot);
+        st->rho_old = st->rho;
+      }
+      st->rho = tot;
+      st->first = 0;
+      st->pending = 0;
+    } else {  // FIN_RES
+      st->outer_rr = tot;
+    }
   }
 }
 
@@ -900,13 +1039,19 @@ hipError_t launch_finalize(int kind, const double* partials, int nparts, int ski
                            int nrhs, hipStream_t s) {
   switch (kind) {
     case FIN_PQ:
-      hipLaunchKernelGGL(k_finalize<FIN_PQ>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      klaunch(k_finalize<FIN_PQ>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
       break;
     case FIN_RR:
-      hipLaunchKernelGGL(k_finalize<FIN_RR>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      klaunch(k_finalize<FIN_RR>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
       break;
     case FIN_RES:
-      hipLaunchKernelGGL(k_finalize<FIN_RES>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      klaunch(k_finalize<FIN_RES>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      break;
+    case FIN_PQF:
+      klaunch(k_finalize<FIN_PQF>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      break;
+    case FIN_RRF:
+      klaunch(k_finalize<FIN_RRF>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -992,7 +1137,7 @@ hipError_t launch_split_fac(int n, const double* lam, double m_cells, double* fa
   const int64_t total = split_fac_elems(n);
   if (total <= 0) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_split_fac, dim3(blocks), dim3(256), 0, s, lam, n / 2 + 1,
+  klaunch(k_split_fac, dim3(blocks), dim3(256), 0, s, lam, n / 2 + 1,
                      (n / 2 + FB) / FB, m_cells, fac64, fac32);
   return hipGetLastError();
 }
@@ -1014,7 +1159,7 @@ hipError_t launch_xlam_rows(int n, const double* lam, double* rows64, float* row
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
   switch (n) {
 #define X(L) \
-  case L: hipLaunchKernelGGL(k_xlam_rows<L>, dim3(blocks), dim3(256), 0, s, lam, rows64, rows32); break;
+  case L: klaunch(k_xlam_rows<L>, dim3(blocks), dim3(256), 0, s, lam, rows64, rows32); break;
     WF_FOR_F32(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -1053,11 +1198,11 @@ static hipError_t zfwd_n(int mode, const ZfwdArgs<T>& a, int64_t nrows, int nrhs
   constexpr int NB = z_nb<T, N>();
   dim3 grid((unsigned)(nrows / (2 * NB)), (unsigned)nrhs);
   switch (mode) {
-    case ZIN_REAL: hipLaunchKernelGGL((k_zfwd<T, N, ZIN_REAL>), grid, dim3(NT), 0, s, a); break;
-    case ZIN_CGP: hipLaunchKernelGGL((k_zfwd<T, N, ZIN_CGP>), grid, dim3(NT), 0, s, a); break;
+    case ZIN_REAL: klaunch((k_zfwd<T, N, ZIN_REAL>), grid, dim3(NT), 0, s, a); break;
+    case ZIN_CGP: klaunch((k_zfwd<T, N, ZIN_CGP>), grid, dim3(NT), 0, s, a); break;
     case ZIN_I64:
       if constexpr (sizeof(T) == 8) {
-        hipLaunchKernelGGL((k_zfwd<T, N, ZIN_I64>), grid, dim3(NT), 0, s, a);
+        klaunch((k_zfwd<T, N, ZIN_I64>), grid, dim3(NT), 0, s, a);
         break;
       }
       return hipErrorInvalidValue;
@@ -1071,15 +1216,15 @@ static hipError_t zinv_n(int mode, const ZinvArgs<T>& a, int64_t nrows, int nrhs
   constexpr int NB = z_nb<T, N>();
   dim3 grid((unsigned)(nrows / (2 * NB)), (unsigned)nrhs);
   switch (mode) {
-    case ZOUT_REAL: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_REAL>), grid, dim3(NT), 0, s, a); break;
-    case ZOUT_CGQ: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_CGQ>), grid, dim3(NT), 0, s, a); break;
+    case ZOUT_REAL: klaunch((k_zinv<T, N, ZOUT_REAL>), grid, dim3(NT), 0, s, a); break;
+    case ZOUT_CGQ: klaunch((k_zinv<T, N, ZOUT_CGQ>), grid, dim3(NT), 0, s, a); break;
     case ZOUT_RES:
       if constexpr (sizeof(T) == 8) {
-        hipLaunchKernelGGL((k_zinv<T, N, ZOUT_RES>), grid, dim3(NT), 0, s, a);
+        klaunch((k_zinv<T, N, ZOUT_RES>), grid, dim3(NT), 0, s, a);
         break;
       }
       return hipErrorInvalidValue;
-    case ZOUT_APPLY: hipLaunchKernelGGL((k_zinv<T, N, ZOUT_APPLY>), grid, dim3(NT), 0, s, a); break;
+    case ZOUT_APPLY: klaunch((k_zinv<T, N, ZOUT_APPLY>), grid, dim3(NT), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1089,7 +1234,7 @@ template <typename T, int N>
 static hipError_t zmid_n(const ZmidArgs<T>& a, int64_t nrows, int nrhs, hipStream_t s) {
   constexpr int NB = z_nb<T, N>();
   dim3 grid((unsigned)(nrows / (2 * NB)), (unsigned)nrhs);
-  hipLaunchKernelGGL((k_zmid<T, N>), grid, dim3(NT), 0, s, a);
+  klaunch((k_zmid<T, N>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1097,14 +1242,25 @@ template <typename T, int N, int TBV, int NTV>
 static hipError_t strided_v(int mode, const StrArgs<T>& a, int nrhs, hipStream_t s) {
   dim3 grid((unsigned)(a.nblk0 + a.nblk1), (unsigned)nrhs);
   switch (mode) {
-    case SM_FWD: hipLaunchKernelGGL((k_strided<T, N, SM_FWD, TBV, NTV>), grid, dim3(NTV), 0, s, a); break;
-    case SM_INV: hipLaunchKernelGGL((k_strided<T, N, SM_INV, TBV, NTV>), grid, dim3(NTV), 0, s, a); break;
+    case SM_FWD: klaunch((k_strided<T, N, SM_FWD, TBV, NTV>), grid, dim3(NTV), 0, s, a); break;
+    case SM_INV: klaunch((k_strided<T, N, SM_INV, TBV, NTV>), grid, dim3(NTV), 0, s, a); break;
     case SM_FWD_LAM_INV:
-      hipLaunchKernelGGL((k_strided<T, N, SM_FWD_LAM_INV, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+      klaunch((k_strided<T, N, SM_FWD_LAM_INV, TBV, NTV>), grid, dim3(NTV), 0, s, a);
       break;
     case SM_FWD_CROP:
-      hipLaunchKernelGGL((k_strided<T, N, SM_FWD_CROP, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+      klaunch((k_strided<T, N, SM_FWD_CROP, TBV, NTV>), grid, dim3(NTV), 0, s, a);
       break;
+    case SM_INV_FOLD:
+    case SM_FWD_CGQF:
+      // the folded iteration exists for FP32 vectors only
+      if constexpr (sizeof(T) == 4) {
+        if (mode == SM_INV_FOLD)
+          klaunch((k_strided<T, N, SM_INV_FOLD, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+        else
+          klaunch((k_strided<T, N, SM_FWD_CGQF, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
     case SM_INV_SCALE:
     case SM_INV_DIR:
     case SM_FWD_SCALE:
@@ -1112,15 +1268,15 @@ static hipError_t strided_v(int mode, const StrArgs<T>& a, int nrhs, hipStream_t
     case SM_FWD_RES:
       if constexpr (N <= 512) {
         if (mode == SM_INV_SCALE)
-          hipLaunchKernelGGL((k_strided<T, N, SM_INV_SCALE, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+          klaunch((k_strided<T, N, SM_INV_SCALE, TBV, NTV>), grid, dim3(NTV), 0, s, a);
         else if (mode == SM_INV_DIR)
-          hipLaunchKernelGGL((k_strided<T, N, SM_INV_DIR, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+          klaunch((k_strided<T, N, SM_INV_DIR, TBV, NTV>), grid, dim3(NTV), 0, s, a);
         else if (mode == SM_FWD_SCALE)
-          hipLaunchKernelGGL((k_strided<T, N, SM_FWD_SCALE, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+          klaunch((k_strided<T, N, SM_FWD_SCALE, TBV, NTV>), grid, dim3(NTV), 0, s, a);
         else if (mode == SM_FWD_CGQ)
-          hipLaunchKernelGGL((k_strided<T, N, SM_FWD_CGQ, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+          klaunch((k_strided<T, N, SM_FWD_CGQ, TBV, NTV>), grid, dim3(NTV), 0, s, a);
         else if constexpr (sizeof(T) == 8)
-          hipLaunchKernelGGL((k_strided<T, N, SM_FWD_RES, TBV, NTV>), grid, dim3(NTV), 0, s, a);
+          klaunch((k_strided<T, N, SM_FWD_RES, TBV, NTV>), grid, dim3(NTV), 0, s, a);
         else
           return hipErrorInvalidValue;
         break;
@@ -1138,7 +1294,8 @@ static hipError_t strided_v(int mode, const StrArgs<T>& a, int nrhs, hipStream_t
 template <typename T, int N>
 static hipError_t strided_n(int mode, const StrArgs<T>& a, int nrhs, hipStream_t s) {
   if constexpr (sizeof(T) == 4 && N >= 256) {
-    if (mode != SM_FWD_CGQ) return strided_v<T, N, str_tb<T, N>(), 1024>(mode, a, nrhs, s);
+    if (mode != SM_FWD_CGQ && mode != SM_FWD_CGQF)
+      return strided_v<T, N, str_tb<T, N>(), 1024>(mode, a, nrhs, s);
   }
   return strided_v<T, N, str_tb<T, N>(), NT_STRIDED>(mode, a, nrhs, s);
 }

@@ -63,10 +63,16 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
-// Live kernel timing: HIP events recorded around launches, harvested at
-// synchronisation points.
+// Live kernel timing with HIP events, harvested at synchronisation points.
+// A bracket of one launch hands its events to that launch, which the runtime
+// stamps with the dispatch's own start and end; a bracket of several launches
+// records the events around them as markers (without the system-scope fence,
+// a cache writeback at each record).  With every > 1 only one bracket in
+// `every` of each class is timed.
 struct Profiler {
   bool on = false;
+  int every = 1;
+  int64_t seen[WF_PROF_KINDS] = {};
   struct Pair {
     hipEvent_t a, b;
     int kind;
@@ -76,13 +82,14 @@ struct Profiler {
   std::vector<Pair> pending;
   std::vector<float> dur[WF_PROF_KINDS];     // ms of every harvested launch
   std::vector<double> byt[WF_PROF_KINDS];
-  // Totals over active launches: a launch shorter than a quarter of its
-  // class's median found its right-hand side already stopped and is skipped.
+  // Totals over full-work launches: a launch shorter than 0.8 of its class's
+  // median did less (right-hand sides already stopped, or a first direction
+  // that reads fewer vectors) and is counted as skipped.
   void totals(int64_t* launches, int64_t* skipped, double* ms, double* bytes) const;
   ~Profiler();
   void clear();
-  int begin(int kind, double bytes, hipStream_t s);
-  void end(int idx, hipStream_t s);
+  int begin(int kind, double bytes, hipStream_t s, bool multi);
+  void end(int idx, hipStream_t s, bool multi);
   void harvest();   // all recorded events must have completed
 };
 
@@ -90,11 +97,13 @@ struct Profiler {
 struct ProfScope {
   Profiler* p;
   hipStream_t s;
+  bool multi;
   int idx;
-  ProfScope(Profiler* p_, int kind, double bytes, hipStream_t s_)
-      : p(p_), s(s_), idx(p_ ? p_->begin(kind, bytes, s_) : -1) {}
+  // multi: the bracket holds more than one launch
+  ProfScope(Profiler* p_, int kind, double bytes, hipStream_t s_, bool multi_ = false)
+      : p(p_), s(s_), multi(multi_), idx(p_ ? p_->begin(kind, bytes, s_, multi_) : -1) {}
   ~ProfScope() {
-    if (p && idx >= 0) p->end(idx, s);
+    if (p && idx >= 0) p->end(idx, s, multi);
   }
 };
 

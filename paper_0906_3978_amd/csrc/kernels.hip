@@ -133,8 +133,8 @@ template <typename T>
 hipError_t launch_cg_flush(T* x, const T* p, int64_t m, int64_t rs, CgState* st, int nrhs,
                            hipStream_t s) {
   dim3 grid(vec_blocks(m), nrhs);
-  hipLaunchKernelGGL(k_cg_flush<T>, grid, dim3(VEC_THREADS), 0, s, x, p, m, rs, st);
-  hipLaunchKernelGGL(k_clear_pending, dim3(nrhs), dim3(64), 0, s, st);
+  klaunch(k_cg_flush<T>, grid, dim3(VEC_THREADS), 0, s, x, p, m, rs, st);
+  klaunch(k_clear_pending, dim3(nrhs), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 template hipError_t launch_cg_flush<float>(float*, const float*, int64_t, int64_t, CgState*, int,
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_state_norm(const double* v, int
 hipError_t launch_state_norm(const double* v, int64_t m, int64_t rs, double* partials,
                              CgState* st, int nrhs, hipStream_t s) {
   dim3 grid(vec_blocks(m), nrhs);
-  hipLaunchKernelGGL(k_state_norm, grid, dim3(VEC_THREADS), 0, s, v, m, rs, partials, st);
+  klaunch(k_state_norm, grid, dim3(VEC_THREADS), 0, s, v, m, rs, partials, st);
   return hipGetLastError();
 }
 
@@ -188,7 +188,7 @@ template <typename T>
 hipError_t launch_cg_init(T* x, T* r, const double* src, int64_t m, int64_t rs,
                           double* partials, CgState* st, int nrhs, hipStream_t s) {
   dim3 grid(vec_blocks(m), nrhs);
-  hipLaunchKernelGGL(k_cg_init<T>, grid, dim3(VEC_THREADS), 0, s, x, r, src, m, rs, partials, st);
+  klaunch(k_cg_init<T>, grid, dim3(VEC_THREADS), 0, s, x, r, src, m, rs, partials, st);
   return hipGetLastError();
 }
 template hipError_t launch_cg_init<float>(float*, float*, const double*, int64_t, int64_t,
@@ -201,9 +201,9 @@ hipError_t launch_cg_update(T* r, const T* q, int64_t m, int64_t rs, double* par
                             CgState* st, int nrhs, hipStream_t s) {
   dim3 grid(update_blocks(m, sizeof(T) == 8), nrhs);
   if (update_k(m, 16 / sizeof(T)) == 8)
-    hipLaunchKernelGGL((k_cg_update<T, 8>), grid, dim3(VEC_THREADS), 0, s, r, q, m, rs, partials, st);
+    klaunch((k_cg_update<T, 8>), grid, dim3(VEC_THREADS), 0, s, r, q, m, rs, partials, st);
   else
-    hipLaunchKernelGGL((k_cg_update<T, 1>), grid, dim3(VEC_THREADS), 0, s, r, q, m, rs, partials, st);
+    klaunch((k_cg_update<T, 1>), grid, dim3(VEC_THREADS), 0, s, r, q, m, rs, partials, st);
   return hipGetLastError();
 }
 template hipError_t launch_cg_update<float>(float*, const float*, int64_t, int64_t, double*,
@@ -272,7 +272,7 @@ hipError_t launch_rel_init(double* x64, double* r64, const double* b, float* x32
                            int64_t m, int64_t rs, double* partials, CgState* st, int nrhs,
                            hipStream_t s) {
   dim3 grid(vec_blocks(m), nrhs);
-  hipLaunchKernelGGL(k_rel_init, grid, dim3(VEC_THREADS), 0, s, x64, r64, b, x32, r32, m, rs,
+  klaunch(k_rel_init, grid, dim3(VEC_THREADS), 0, s, x64, r64, b, x32, r32, m, rs,
                      partials, st);
   return hipGetLastError();
 }
@@ -348,24 +348,32 @@ hipError_t launch_rel_fold(double* x64, float* x32, const float* p32, int64_t m,
                            double* partials, const double* fac, int n, int64_t spec_main,
                            int64_t fac_rs, CgState* st, int nrhs, hipStream_t s) {
   dim3 grid(vec_blocks(m), nrhs);
-  hipLaunchKernelGGL(k_rel_fold, grid, dim3(VEC_THREADS), 0, s, x64, x32, p32, m, rs, partials,
+  klaunch(k_rel_fold, grid, dim3(VEC_THREADS), 0, s, x64, x32, p32, m, rs, partials,
                      fac, n, spec_main, fac_rs, st);
   return hipGetLastError();
 }
 
+// With p32 (the folded FP32 iteration, whose direction for the next step is
+// already formed when the update falls due): that direction continues with
+// the refreshed residual, p += r_new - r_old; when the update came between
+// iterations instead (x += alpha p still pending, folded by the update), the
+// next direction restarts from r.
 __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const double* r64,
-                                                           int64_t m, int64_t rs, double* partials,
-                                                           CgState* st_all) {
+                                                           float* p32, int64_t m, int64_t rs,
+                                                           double* partials, CgState* st_all) {
   __shared__ double red[VEC_THREADS / 64];
   __shared__ int last_flag;
   const int rhs = blockIdx.y;
   CgState* st = st_all + rhs;
   if (st->status != CG_UPDATE) return;
+  const bool was_pending = st->pending != 0;
+  const bool carry = p32 != nullptr && !was_pending;
   const int64_t o = rhs * rs;
   double rr = 0.0;
   const int64_t stride = (int64_t)gridDim.x * VEC_THREADS;
   for (int64_t i = (int64_t)blockIdx.x * VEC_THREADS + threadIdx.x; i < m; i += stride) {
     const float f = (float)r64[o + i];
+    if (carry) p32[o + i] += f - r32[o + i];
     r32[o + i] = f;
     rr += (double)f * (double)f;
   }
@@ -374,6 +382,9 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const dou
   if (publish_partial(part, parts, &st->ticket, gridDim.x, &last_flag)) {
     const double tot = reduce_partials(parts, gridDim.x, red);
     if (threadIdx.x == 0) {
+      // the folded iteration counts a step when the next iteration applies
+      // it; a step the fold applied instead counts here
+      if (p32 && was_pending) st->iter += 1;
       st->updates += 1;
       st->upd_iter = st->iter;
       st->pending = 0;  // folded
@@ -420,6 +431,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const dou
         // the residual met but the solution still moving, the next update
         // comes when the residual has dropped by delta again
         st->beta = tot / st->rho_old;
+        if (p32) st->first = was_pending ? 1 : 0;
         st->rho = tot;
         st->rmax = sqrt(tot);
         st->rel = sqrt(tot) / st->bnorm;
@@ -431,10 +443,10 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_reset(float* r32, const dou
   }
 }
 
-hipError_t launch_rel_reset(float* r32, const double* r64, int64_t m, int64_t rs,
+hipError_t launch_rel_reset(float* r32, const double* r64, float* p32, int64_t m, int64_t rs,
                             double* partials, CgState* st, int nrhs, hipStream_t s) {
   dim3 grid(vec_blocks(m), nrhs);
-  hipLaunchKernelGGL(k_rel_reset, grid, dim3(VEC_THREADS), 0, s, r32, r64, m, rs, partials, st);
+  klaunch(k_rel_reset, grid, dim3(VEC_THREADS), 0, s, r32, r64, p32, m, rs, partials, st);
   return hipGetLastError();
 }
 
@@ -458,7 +470,7 @@ __global__ void k_state_init(CgState* st_all, const double* nbar, double tol, in
 hipError_t launch_state_init(CgState* st, const double* nbar, double tol, int32_t max_iter,
                              double delta, int32_t max_updates, double err_tol, int nrhs,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_state_init, dim3(nrhs), dim3(64), 0, s, st, nbar, tol, max_iter, delta,
+  klaunch(k_state_init, dim3(nrhs), dim3(64), 0, s, st, nbar, tol, max_iter, delta,
                      max_updates, err_tol);
   return hipGetLastError();
 }
@@ -482,12 +494,12 @@ __global__ void k_state_request_update(CgState* st) {
 }
 
 hipError_t launch_state_request_update(CgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_request_update, dim3(1), dim3(64), 0, s, st);
+  klaunch(k_state_request_update, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 
 hipError_t launch_state_stop(CgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_stop, dim3(1), dim3(64), 0, s, st);
+  klaunch(k_state_stop, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 
@@ -505,15 +517,15 @@ static dim3 fill_grid(int64_t n) {
   return dim3((unsigned)b);
 }
 hipError_t launch_fill_i64(long long* p, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill<long long>, fill_grid(n), dim3(256), 0, s, p, n, 0LL);
+  klaunch(k_fill<long long>, fill_grid(n), dim3(256), 0, s, p, n, 0LL);
   return hipGetLastError();
 }
 hipError_t launch_fill_c64(double2* p, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill<double2>, fill_grid(n), dim3(256), 0, s, p, n, double2{0.0, 0.0});
+  klaunch(k_fill<double2>, fill_grid(n), dim3(256), 0, s, p, n, double2{0.0, 0.0});
   return hipGetLastError();
 }
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill<double>, fill_grid(n), dim3(256), 0, s, p, n, 0.0);
+  klaunch(k_fill<double>, fill_grid(n), dim3(256), 0, s, p, n, 0.0);
   return hipGetLastError();
 }
 
@@ -524,16 +536,16 @@ __global__ void k_convert(O* out, const I* in, double unit, int64_t n) {
     out[i] = (O)((double)in[i] * unit);
 }
 hipError_t launch_f64_to_f32(float* out, const double* in, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_convert<float, double>), fill_grid(n), dim3(256), 0, s, out, in, 1.0, n);
+  klaunch((k_convert<float, double>), fill_grid(n), dim3(256), 0, s, out, in, 1.0, n);
   return hipGetLastError();
 }
 hipError_t launch_f32_to_f64(double* out, const float* in, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_convert<double, float>), fill_grid(n), dim3(256), 0, s, out, in, 1.0, n);
+  klaunch((k_convert<double, float>), fill_grid(n), dim3(256), 0, s, out, in, 1.0, n);
   return hipGetLastError();
 }
 hipError_t launch_i64_to_f64(double* out, const long long* in, double unit, int64_t n,
                              hipStream_t s) {
-  hipLaunchKernelGGL((k_convert<double, long long>), fill_grid(n), dim3(256), 0, s, out, in, unit,
+  klaunch((k_convert<double, long long>), fill_grid(n), dim3(256), 0, s, out, in, unit,
                      n);
   return hipGetLastError();
 }
@@ -551,7 +563,7 @@ __global__ void k_check_xyz(const double* xyz, int64_t n3, double box, int* flag
 
 hipError_t launch_check_xyz(const double* xyz, int64_t ngal, double box, int* flag, hipStream_t s) {
   if (ngal <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_check_xyz, fill_grid(3 * ngal), dim3(256), 0, s, xyz, 3 * ngal, box, flag);
+  klaunch(k_check_xyz, fill_grid(3 * ngal), dim3(256), 0, s, xyz, 3 * ngal, box, flag);
   return hipGetLastError();
 }
 
@@ -597,9 +609,9 @@ hipError_t launch_deposit(int scheme, const double* xyz, int64_t ngal, double c,
   dim3 gridd((unsigned)((ngal + 255) / 256));
   auto* gp = reinterpret_cast<unsigned long long*>(grid);
   switch (scheme) {
-    case 0: hipLaunchKernelGGL(k_deposit<0>, gridd, dim3(256), 0, s, xyz, ngal, c, nd, gp); break;
-    case 1: hipLaunchKernelGGL(k_deposit<1>, gridd, dim3(256), 0, s, xyz, ngal, c, nd, gp); break;
-    case 2: hipLaunchKernelGGL(k_deposit<2>, gridd, dim3(256), 0, s, xyz, ngal, c, nd, gp); break;
+    case 0: klaunch(k_deposit<0>, gridd, dim3(256), 0, s, xyz, ngal, c, nd, gp); break;
+    case 1: klaunch(k_deposit<1>, gridd, dim3(256), 0, s, xyz, ngal, c, nd, gp); break;
+    case 2: klaunch(k_deposit<2>, gridd, dim3(256), 0, s, xyz, ngal, c, nd, gp); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -636,7 +648,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_mask(const double* w, double* w
 
 hipError_t launch_mask(const double* w, double* w64, float* w32, int64_t m, int* flag,
                        double* partials, uint32_t* ticket, double* sumw, hipStream_t s) {
-  hipLaunchKernelGGL(k_mask, dim3(vec_blocks(m)), dim3(VEC_THREADS), 0, s, w, w64, w32, m, flag,
+  klaunch(k_mask, dim3(vec_blocks(m)), dim3(VEC_THREADS), 0, s, w, w64, w32, m, flag,
                      partials, ticket, sumw);
   return hipGetLastError();
 }
@@ -658,7 +670,7 @@ __global__ void k_lambda(const double* p, int64_t len, double dv, double inv_m, 
 
 hipError_t launch_lambda(const double* p, int64_t len, double dv, double inv_m, double* lam64,
                          int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_lambda, fill_grid(len), dim3(256), 0, s, p, len, dv, inv_m, lam64, flag);
+  klaunch(k_lambda, fill_grid(len), dim3(256), 0, s, p, len, dv, inv_m, lam64, flag);
   return hipGetLastError();
 }
 
@@ -675,7 +687,7 @@ __global__ void k_data_vector(const double* nobs, const double* w, const double*
 
 hipError_t launch_data_vector(const double* nobs, const double* w, const double* sumw, double ngal,
                               double* nbar_out, double* b, int64_t m, hipStream_t s) {
-  hipLaunchKernelGGL(k_data_vector, fill_grid(m), dim3(256), 0, s, nobs, w, sumw, ngal, nbar_out,
+  klaunch(k_data_vector, fill_grid(m), dim3(256), 0, s, nobs, w, sumw, ngal, nbar_out,
                      b, m);
   return hipGetLastError();
 }

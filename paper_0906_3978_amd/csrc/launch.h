@@ -1,12 +1,34 @@
 // Kernel argument blocks and launchers (host side of kernels.hip).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "common.h"
 
 namespace wf {
+
+// ---- live timing ------------------------------------------------------------
+// A profiler arms a pair of events; the next kernel launch of this thread
+// takes them, and the runtime stamps them with that dispatch's own start and
+// end (no marker packets enter the queue, so timing costs the work nothing).
+struct TimedLaunch {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+TimedLaunch& timed_launch();
+
+template <typename F, typename... Args>
+inline void klaunch(F kernel, const dim3& grid, const dim3& block, uint32_t shm, hipStream_t s,
+                    Args... args) {
+  TimedLaunch& t = timed_launch();
+  if (t.start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, s, t.start, t.stop, 0, args...);
+    t.start = t.stop = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+  }
+}
 
 // ---- z-axis passes (contiguous rows, real <-> half spectrum) --------------
 enum ZinMode : int { ZIN_REAL = 0, ZIN_CGP = 1, ZIN_I64 = 2 };
@@ -72,9 +94,13 @@ template <typename T> struct ZmidArgs {
 // makes their plain dot products the full-spectrum inner products.
 // INV_DIR is INV_SCALE of the CG direction, formed on the way in: `in` is r,
 // the pending x += alpha p is applied and p = r + beta p written back (Seg p, x).
+// INV_FOLD (FP32 prior-split CG) also applies the pending r -= alpha q (Seg r,
+// q) before the direction and writes the block partials of the new r.r;
+// FWD_CGQF is FWD_CGQ that also sums q.q (two partials per block).
 enum StrMode : int {
   SM_FWD = 0, SM_INV = 1, SM_FWD_LAM_INV = 2, SM_FWD_CROP = 3,
-  SM_INV_SCALE = 4, SM_FWD_SCALE = 5, SM_FWD_CGQ = 6, SM_FWD_RES = 7, SM_INV_DIR = 8
+  SM_INV_SCALE = 4, SM_FWD_SCALE = 5, SM_FWD_CGQ = 6, SM_FWD_RES = 7, SM_INV_DIR = 8,
+  SM_INV_FOLD = 9, SM_FWD_CGQF = 10
 };
 
 template <typename T> struct Seg {
@@ -90,6 +116,8 @@ template <typename T> struct Seg {
   const cplx<double>* bvec; // split RES: b at the output's positions
   cplx<T>* p;               // split INV_DIR: direction and iterate at the input's positions
   cplx<T>* x;
+  cplx<T>* r;               // split INV_FOLD: residual (written back) and q
+  const cplx<T>* q;
 };
 
 template <typename T> struct StrArgs {
@@ -102,7 +130,8 @@ template <typename T> struct StrArgs {
   const T* fac;             // split modes: c over (|my|, |mx|, kz), in blocks of 16 kz:
                             // [|my|][kz / 16][|mx|][kz % 16]
   double in_scale;          // SM_INV_SCALE: 1 / M
-  double* partials;         // SM_FWD_CGQ / SM_FWD_RES: per RHS, one per block
+  double* partials;         // SM_FWD_CGQ / SM_FWD_RES / SM_INV_FOLD: per RHS, one per
+                            // block; SM_FWD_CGQF: per RHS, p.q of every block, then q.q
   int64_t rhs_lam, rhs_fac; // per-RHS strides of lam and fac (0: shared)
 };
 
@@ -122,8 +151,11 @@ template <typename T> hipError_t launch_zmid(int n, const ZmidArgs<T>& a, int64_
 
 // Sums the block partials of one reduction (nparts per RHS, fixed order) and
 // updates the CG state: FIN_PQ -> alpha (or breakdown), FIN_RR -> iteration
-// bookkeeping, beta and stopping, FIN_RES -> outer_rr.
-enum FinKind : int { FIN_PQ = 0, FIN_RR = 1, FIN_RES = 2 };
+// bookkeeping, beta and stopping, FIN_RES -> outer_rr.  The folded FP32
+// prior-split iteration uses FIN_RRF after INV_FOLD (the new r.r: iteration
+// bookkeeping and stopping) and FIN_PQF after FWD_CGQF (alpha, and beta from
+// r.r - 2 alpha p.q + alpha^2 q.q with p.q standing in for r.q).
+enum FinKind : int { FIN_PQ = 0, FIN_RR = 1, FIN_RES = 2, FIN_PQF = 3, FIN_RRF = 4 };
 hipError_t launch_finalize(int kind, const double* partials, int nparts, int skip, CgState* st,
                            int nrhs, hipStream_t s);
 
@@ -159,9 +191,11 @@ hipError_t launch_rel_fold(double* x64, float* x32, const float* p32, int64_t m,
                            int64_t spec_main, int64_t fac_rs, CgState* st, int nrhs,
                            hipStream_t s);
 // RHS waiting for an update (after r64 = b - A64 x64): r32 = (float) r64, rho,
-// convergence test on the FP64 residual, resume or stop
-hipError_t launch_rel_reset(float* r32, const double* r64, int64_t m, int64_t rhs_stride,
-                            double* partials, CgState* st, int nrhs, hipStream_t s);
+// convergence test on the FP64 residual, resume or stop.  p32 (folded FP32
+// iteration only, else null): the formed direction continues with the new r.
+hipError_t launch_rel_reset(float* r32, const double* r64, float* p32, int64_t m,
+                            int64_t rhs_stride, double* partials, CgState* st, int nrhs,
+                            hipStream_t s);
 
 // state of nrhs solves from device-resident nbar values
 hipError_t launch_state_init(CgState* st, const double* nbar, double tol, int32_t max_iter,

@@ -73,21 +73,30 @@ Status cg_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hi
 }
 
 // One CG iteration of the prior-split system; vectors are half spectra.
+// FP32 (the inner iteration of mixed solves) folds the residual update into
+// the first pass of the next iteration: the x pass that forms the direction
+// also applies r -= alpha q, and beta comes from p.q and q.q (see FIN_PQF),
+// which saves the separate update kernel's sweep over r and q.  The
+// iteration in which a reliable update falls due has already formed its
+// direction; the update continues that direction (see k_rel_reset).
 template <typename T>
 Status split_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hipStream_t s) {
   CgState* st = sw.state.as<CgState>();
   double* parts = sw.partials.as<double>();
-  const int64_t vl = sw.vlen;
-  const bool f64 = sizeof(T) == 8;
-  WF_TRY(split_passes<T>(od, SM_FWD_CGQ, v.p, v.spec, v.q, nullptr, st, parts, nr, SKIP_DONE, s,
-                         v.r, v.x));
-  {
-    ProfScope ps(od.prof, f64 ? WF_PROF_UPDATE_F64 : WF_PROF_UPDATE_F32, 3.0 * sizeof(T) * vl * nr,
-                 s);
-    WF_HIP(launch_cg_update<T>(v.r, v.q, vl, vl, parts, st, nr, s));
+  if constexpr (sizeof(T) == 4) {
+    return split_passes<T>(od, SM_FWD_CGQF, v.p, v.spec, v.q, nullptr, st, parts, nr, SKIP_DONE,
+                           s, v.r, v.x);
+  } else {
+    const int64_t vl = sw.vlen;
+    WF_TRY(split_passes<T>(od, SM_FWD_CGQ, v.p, v.spec, v.q, nullptr, st, parts, nr, SKIP_DONE,
+                           s, v.r, v.x));
+    {
+      ProfScope ps(od.prof, WF_PROF_UPDATE_F64, 3.0 * sizeof(T) * vl * nr, s);
+      WF_HIP(launch_cg_update<T>(v.r, v.q, vl, vl, parts, st, nr, s));
+    }
+    WF_HIP(launch_finalize(FIN_RR, parts, update_blocks(vl, true), SKIP_DONE, st, nr, s));
+    return {};
   }
-  WF_HIP(launch_finalize(FIN_RR, parts, update_blocks(vl, f64), SKIP_DONE, st, nr, s));
-  return {};
 }
 
 template <typename T>
@@ -234,7 +243,8 @@ Status solve_update(const OperatorData& od, SolveWork& sw, int nr, hipStream_t s
                                    sw.x64.as<double>(), sw.b64.as<double>(), st, parts, nr,
                                    SKIP_UNLESS_UPDATE, s));
   }
-  WF_HIP(launch_rel_reset(sw.r32.as<float>(), sw.r64.as<double>(), vl, vl, parts, st, nr, s));
+  WF_HIP(launch_rel_reset(sw.r32.as<float>(), sw.r64.as<double>(),
+                          sw.split ? sw.p32.as<float>() : nullptr, vl, vl, parts, st, nr, s));
   return {};
 }
 
@@ -353,19 +363,25 @@ Status step_iterations(const OperatorData& od, SolveWork& sw, int iters, bool mi
   }
   // FP32 iterations until `iters` more have run or the solve stops, with the
   // reliable updates the state asks for on the way (the device decides when;
-  // how the host chunks its launches changes nothing)
+  // how the host chunks its launches changes nothing).  The folded
+  // prior-split iteration ends with its step pending, counted by the next
+  // one: a pending step counts as done here.
   WF_TRY(sw.pull_state(s));
-  const int64_t target = (int64_t)sw.st_host[0].iter + iters;
+  const bool fold = sw.split;
+  auto steps = [fold](const CgState& c) {
+    return (int64_t)c.iter + (fold && c.pending && !c.done ? 1 : 0);
+  };
+  const int64_t target = steps(sw.st_host[0]) + iters;
   Vecs<float> v = v32(sw);
   for (;;) {
     const CgState& c = sw.st_host[0];
-    if (c.iter >= target) return {};
+    if (steps(c) >= target) return {};
     if (c.status == CG_UPDATE) {
       WF_TRY(solve_update(od, sw, 1, s));
     } else if (c.done) {
       return {};
     } else {
-      const int64_t left = target - c.iter;
+      const int64_t left = target - steps(c);
       for (int64_t k = 0; k < std::min<int64_t>(left, 16); ++k)
         WF_TRY(any_iteration<float>(od, sw, v, 1, s));
     }
@@ -400,10 +416,10 @@ struct SnapHeader {
   int32_t n;
   int32_t split;  // 1: prior-split solve (the vectors are half spectra)
   double box;
-  int32_t mixed;  // 1: mixed precision (FP64 x, r; FP32 x, r, p)
+  int32_t mixed;  // 1: mixed precision (FP64 x, r; FP32 x, r, p and, prior-split, q)
   int32_t pad;
 };
-constexpr uint64_t SNAP_MAGIC = 0x5746534e41503032ull;  // "WFSNAP02"
+constexpr uint64_t SNAP_MAGIC = 0x5746534e41503033ull;  // "WFSNAP03"
 }  // namespace
 
 static size_t vector_len(const Grid& g, bool split) {
@@ -412,7 +428,8 @@ static size_t vector_len(const Grid& g, bool split) {
 
 size_t snapshot_bytes(const Grid& g, bool split, bool mixed) {
   const size_t v = vector_len(g, split);
-  return sizeof(SnapHeader) + sizeof(CgState) + (mixed ? 2 * v * 8 + 3 * v * 4 : 3 * v * 8);
+  return sizeof(SnapHeader) + sizeof(CgState) +
+         (mixed ? 2 * v * 8 + (split ? 4 : 3) * v * 4 : 3 * v * 8);
 }
 
 bool snapshot_kind(const void* buf, bool* split, bool* mixed) {
@@ -424,8 +441,12 @@ bool snapshot_kind(const void* buf, bool* split, bool* mixed) {
   return true;
 }
 
-// the device vectors of a snapshot, in order, and their element sizes
+// the device vectors of a snapshot, in order, and their element sizes (the
+// folded FP32 prior-split iteration keeps r -= alpha q pending between
+// iterations, so its snapshot holds q as well)
 static std::vector<std::pair<DevBuf*, size_t>> snap_vectors(SolveWork& sw, bool mixed) {
+  if (mixed && sw.split)
+    return {{&sw.x64, 8}, {&sw.r64, 8}, {&sw.x32, 4}, {&sw.r32, 4}, {&sw.p32, 4}, {&sw.q32, 4}};
   if (mixed) return {{&sw.x64, 8}, {&sw.r64, 8}, {&sw.x32, 4}, {&sw.r32, 4}, {&sw.p32, 4}};
   return {{&sw.x64, 8}, {&sw.r64, 8}, {&sw.p64, 8}};
 }
