@@ -1287,15 +1287,20 @@ static hipError_t strided_v(int mode, const StrArgs<T>& a, int nrhs, hipStream_t
   return hipGetLastError();
 }
 
-// FP32 tiles of the large grids run 1024 threads (four 16-byte loads per
-// thread and array instead of eight, one block of 16 waves per CU instead of
-// two of 8): at 512^3 the y passes and the x inverse with the CG direction
-// are 3-4 % faster; the x forward with q is not, and keeps 512.
+// Tiles of the large grids run 1024 threads (half the loads per thread and
+// array, two blocks of 16 waves per CU instead of two of 8).  Measured at
+// 512^3: FP32, the y passes and the x inverse with the CG direction are
+// 3-4 % faster, the x forward with q is slower (its 1024-thread form spills
+// under the 64-VGPR cap) and keeps 512; FP64, the y passes and the plain x
+// pass are 3-4 % faster, the x passes of the split CG (direction, q,
+// residual) are not and keep 512.
 template <typename T, int N>
 static hipError_t strided_n(int mode, const StrArgs<T>& a, int nrhs, hipStream_t s) {
-  if constexpr (sizeof(T) == 4 && N >= 256) {
-    if (mode != SM_FWD_CGQ && mode != SM_FWD_CGQF)
-      return strided_v<T, N, str_tb<T, N>(), 1024>(mode, a, nrhs, s);
+  if constexpr (N >= 256) {
+    const bool wide = sizeof(T) == 4 ? (mode != SM_FWD_CGQ && mode != SM_FWD_CGQF)
+                                     : (mode != SM_INV_DIR && mode != SM_FWD_CGQ &&
+                                        mode != SM_FWD_RES);
+    if (wide) return strided_v<T, N, str_tb<T, N>(), 1024>(mode, a, nrhs, s);
   }
   return strided_v<T, N, str_tb<T, N>(), NT_STRIDED>(mode, a, nrhs, s);
 }
