@@ -559,6 +559,8 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
   const bool f64 = sizeof(T) == 8;
   const double vb = (double)sizeof(T) * g.m * nrhs;
   const double sb = 2.0 * sizeof(T) * g.spec_total * nrhs;
+  // each x pass reads the factor table once (per RHS when each has its own)
+  const double fb = (double)sizeof(T) * split_fac_elems(g.n) * (od.rhs_fac ? nrhs : 1);
   const cplx<T>* pc = reinterpret_cast<const cplx<T>*>(pin);
   if (rdir && mode == SM_FWD_CGQF) {
     // folded CG: r, q, p, x in; r, p, x and the x-transformed work spectrum
@@ -574,13 +576,13 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
     xa.s0.q = reinterpret_cast<const cplx<T>*>(out);
     xa.s1.q = xa.s0.q + g.spec_main;
     {
-      ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 8 * sb, s);
+      ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 8 * sb + fb, s);
       WF_HIP(launch_strided<T>(g.n, SM_INV_FOLD, xa, nrhs, s));
     }
     WF_HIP(launch_finalize(FIN_RRF, partials, xa.nblk0 + xa.nblk1, skip, st, nrhs, s));
   } else if (rdir) {
     // CG: r, p, x in; p, x and the x-transformed work spectrum out
-    ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 6 * sb, s);
+    ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 6 * sb + fb, s);
     StrArgs<T> xa = split_x_args<T>(od, reinterpret_cast<const cplx<T>*>(rdir), work, nullptr,
                                     nullptr, st, skip, nullptr);
     xa.s0.p = const_cast<cplx<T>*>(pc);
@@ -590,7 +592,7 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
     WF_HIP(launch_strided<T>(g.n, SM_INV_DIR, xa, nrhs, s));
   } else {
     // p in, scaled and transformed along x into the work spectrum
-    ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 2 * sb, s);
+    ProfScope ps(od.prof, f64 ? WF_PROF_SXINV_F64 : WF_PROF_SXINV_F32, 2 * sb + fb, s);
     WF_HIP(launch_strided<T>(g.n, SM_INV_SCALE,
                              split_x_args<T>(od, pc, work, nullptr, nullptr, st, skip, nullptr),
                              nrhs, s));
@@ -624,7 +626,7 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
                                         partials);
   {
     // work spectrum in, result out; CGQ also reads p, RES y and b (FP64)
-    double xb = 2 * sb;
+    double xb = 2 * sb + fb;
     if (mode == SM_FWD_CGQ || mode == SM_FWD_CGQF) xb += sb;
     if (mode == SM_FWD_RES) xb += 2 * sb;
     ProfScope ps(od.prof, f64 ? WF_PROF_SXFWD_F64 : WF_PROF_SXFWD_F32, xb, s);
