@@ -51,4 +51,5 @@ def test_cpu_baseline_phases_on_a_small_workload():
         assert ph["cg_iterations_timed"] == 4 and ph["cg_iterations_extrapolated"] == 40
         assert min(ph["deposit"], ph["lowpass"], ph["cg_iteration"]) > 0
         total = ph["deposit"] + ph["lowpass"] + ph["data_vector"] + 40 * ph["cg_iteration"]
-        assert abs(1.0 / base["value"] - total) < 0.01 * total + 1e-3
+        # the phases are reported rounded (1 ms, the iteration 0.1 ms)
+        assert abs(1.0 / base["value"] - total) < 0.01 * total + 3 * 5e-4 + 40 * 5e-5
