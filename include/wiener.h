@@ -443,7 +443,10 @@ typedef struct {
  * precision and preconditioning (up to 16, as many as fit; masks, priors,
  * boxes and catalogues may all differ) as one batched solve, whose every pass
  * is one launch for all of them.  Batched solves run concurrently on their
- * own streams (max_active of them); Krylov state stays on the device; a request's result
+ * own streams (max_active of them).  With max_active > 1 the last free stream
+ * only takes requests of grids up to 128^3 (the first such request in the
+ * queue heads the batch), so small requests never wait behind large solves;
+ * larger ones wait for another stream.  Krylov state stays on the device; a request's result
  * is copied out as soon as its own solve stops, and its gridding buffers are
  * returned as soon as its data vector is built.  A result is bitwise the same
  * whatever it was batched with.  wf_server_submit returns WF_ENOMEM if the

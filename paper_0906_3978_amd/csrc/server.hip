@@ -49,6 +49,11 @@ void* arena_alloc(size_t bytes, void* user) { return static_cast<Arena*>(user)->
 void arena_free(void* p, void* user) { static_cast<Arena*>(user)->put(p); }
 
 constexpr int MAX_COHORT = 16;   // requests per batched solve
+// With more than one stream, the last free stream takes only requests of
+// grids up to SMALL_N^3: a small request then never waits behind large
+// solves (tens of ms against hundreds), and large ones still have the other
+// streams, which are enough to keep HBM busy.
+constexpr int SMALL_N = 128;
 
 enum JobPhase : int { J_QUEUED = 0, J_ACTIVE, J_DONE, J_FAILED };
 enum SlotPhase : int { S_RUNNING = 0, S_COPYING, S_DONE, S_FAILED };
@@ -297,11 +302,13 @@ Status wf_server::setup(Cohort& c) {
   return {};
 }
 
-// Admits the request at the head of the queue together with every queued
-// request of the same kind (up to the free slots), as many of them as fit in
-// the arena; returns true if a cohort was started or a request retired.
+// Admits the first queued request (when only the reserved stream is free, the
+// first small one) together with every queued request of the same kind (up
+// to MAX_COHORT), as many of them as fit in the arena; returns true if a
+// cohort was started or a request retired.
 bool wf_server::admit_some() {
   std::vector<std::shared_ptr<Job>> cand;
+  std::shared_ptr<Job> head;
   hipStream_t st = nullptr;
   {
     std::lock_guard<std::mutex> g(mu);
@@ -315,7 +322,13 @@ bool wf_server::admit_some() {
       j->phase.store(J_FAILED);
     }
     if (queue.empty() || streams.empty()) return false;
-    const auto& head = queue.front();
+    const bool reserved = max_active > 1 && streams.size() == 1;
+    for (const auto& j : queue) {
+      if (j->cancelled.load() || (reserved && j->n > SMALL_N)) continue;
+      head = j;
+      break;
+    }
+    if (!head) return false;  // only large requests wait: the last stream is kept
     for (const auto& j : queue) {
       if ((int)cand.size() >= MAX_COHORT) break;
       if (!j->cancelled.load() && same_key(*head, *j)) cand.push_back(j);
@@ -343,11 +356,9 @@ bool wf_server::admit_some() {
     }
     if (!idle) return false;  // wait for memory to come back
     // nothing will free memory: the head request cannot run
-    std::shared_ptr<Job> head;
     {
       std::lock_guard<std::mutex> g(mu);
-      head = queue.front();
-      queue.pop_front();
+      queue.erase(std::find(queue.begin(), queue.end(), head));
     }
     fail_job(head, why.code, why.msg);
     return true;

@@ -165,3 +165,26 @@ def test_queued_requests_of_equal_kind_share_one_batched_solve():
         assert ig.status == WF_OK
         assert ig.iters_total == ia.iters_total
         assert np.array_equal(xa, xg)
+
+
+def test_small_requests_do_not_wait_behind_large_ones():
+    """With two streams, one running a 192^3 solve, the last free stream is
+    kept for small grids: a 32^3 request submitted after a second 192^3 one
+    is served at once, while the second large request waits for the first."""
+    import paper_0906_3978_amd as wf
+    reqs = []
+    for i, n in enumerate([192, 192, 32]):
+        wl = synth.serving_request(i, base_seed=9300, box=400.0, grids=(n,))
+        wl.n_target = min(wl.n_target, 200_000)
+        p, w = wl.ptab(), wl.mask()
+        reqs.append((wl, p, w, wl.catalogue(p, w).xyz))
+    kw = dict(precision="mixed", precond="prior", tol=1e-6, max_iter=100000)
+    with wf.Server(0, hbm_budget=16 << 30, max_active=2) as srv:
+        ts = [srv.submit(wl.n, wl.box, w, p, xyz, "cic", 2, **kw) for wl, p, w, xyz in reqs]
+        got = [srv.wait(t, wl.n) for t, (wl, _, _, _) in zip(ts, reqs)]
+        st = srv.stats()
+    (_, l1), (_, l2), (_, s) = got
+    print(f"latency ms: large {l1.latency_ms:.1f}, {l2.latency_ms:.1f}; small {s.latency_ms:.1f}")
+    assert all(i.status == WF_OK for _, i in got)
+    assert st["cohorts"] == 3 and st["failed"] == 0
+    assert s.latency_ms < l1.latency_ms < l2.latency_ms
