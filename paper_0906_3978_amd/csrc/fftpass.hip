@@ -744,12 +744,15 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
     }
   }
   load_twiddles<T, N, NT>(twl, a.tw);
-  // split CGQ / RES: the aux vector at the output's positions, requested
-  // before the FFT so that the loads complete under it (VEC tiles of up to
-  // 512 threads; with 1024 the registers are short and other waves hide the
-  // loads, issued after the FFT)
+  // split CGQ / RES: the aux vector and the prior-split factors at the
+  // output's positions, requested before the FFT so that the loads complete
+  // under it (VEC tiles of up to 512 threads; with 1024 the registers are
+  // short and other waves hide the loads, issued after the FFT).  Measured at
+  // 512^3: the factors read here instead of after the FFT make the x forward
+  // with q 7 % faster.
   constexpr bool PRELOAD = REDUCE && VEC && NT <= 512;
   R avp[PRELOAD ? PER : 1];
+  T fpre[PRELOAD ? PER : 1][CW];
   if constexpr (PRELOAD) {
 #pragma unroll
     for (int c = 0; c < PER; ++c) {
@@ -758,6 +761,9 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
         const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
         avp[c] = ld16x<NTA>(reinterpret_cast<const T*>(
             s.aux + rhs * s.out_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i)));
+        int kzp[CW];
+        bool dcp[CW];
+        split_facs<T, N, CW>(fac_r, s, outer, b0 + b, i, fpre[c], kzp, dcp);
       }
     }
   }
@@ -850,6 +856,10 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
           int kz[CW];
           bool dc[CW];
           split_facs<T, N, CW>(fac_r, s, outer, b0 + b, i, f, kz, dc);
+          if constexpr (PRELOAD) {
+#pragma unroll
+            for (int j = 0; j < CW; ++j) f[j] = fpre[c][j];  // (the loads above fold away)
+          }
           R o;
 #pragma unroll
           for (int j = 0; j < CW; ++j) {
