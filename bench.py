@@ -425,7 +425,7 @@ def batch_run(nrhs, tol, precond="prior"):
     if it:
         it["bytes_per_cell_per_rhs"] = round(it["bytes"] / (nrhs * wl.n ** 3), 2)
         it["model_ms_survey"] = round(76.25 * nrhs * wl.n ** 3 / (HBM_PEAK_GBS * 1e9) * 1e3, 3)
-        it["model_ms_fold"] = round(72.0 * nrhs * wl.n ** 3 / (HBM_PEAK_GBS * 1e9) * 1e3, 3)
+        it["model_ms_fold"] = round(68.0 * nrhs * wl.n ** 3 / (HBM_PEAK_GBS * 1e9) * 1e3, 3)
     t = time.perf_counter()
     singles = []
     one = torch.empty((wl.n,) * 3, dtype=torch.float64, device=dev)

@@ -68,6 +68,7 @@ struct CgState {
   int32_t stagnated; // 1: stopped because the FP64 residual no longer falls
   int32_t upd_iter;  // iteration count at the last reliable update
   int32_t win;       // updates summed into move_acc in the current window
+  double pp;         // folded FP32 iteration: p.p of the direction without its monopole
 };
 
 // Reliable updates in a row that do not bring the FP64 residual 10 % below

@@ -239,8 +239,7 @@ Status SolveWork::ensure(const Allocator& al, const Grid& g, int nr, bool fp64_c
     WF_TRY(u64.ensure(al, m * 8));
   }
   // partials: enough for the largest grid of any reduction kernel per RHS
-  const int64_t zblocks = g.nrows / 2;  // upper bound of z-pass blocks (NB >= 1)
-  const int64_t per = std::max<int64_t>(zblocks, 4096);
+  const int64_t per = partials_per_rhs(g);
   WF_TRY(partials.ensure(al, (size_t)per * nr * 8));
   WF_TRY(state.ensure(al, sizeof(CgState) * nr));
   if (st_cap < nr) {
@@ -250,6 +249,11 @@ Status SolveWork::ensure(const Allocator& al, const Grid& g, int nr, bool fp64_c
     st_cap = nr;
   }
   return {};
+}
+
+int64_t partials_per_rhs(const Grid& g) {
+  const int64_t zblocks = g.nrows / 2;  // upper bound of z-pass blocks (NB >= 1)
+  return std::max<int64_t>(zblocks, 4096);
 }
 
 Status SolveWork::pull_state(hipStream_t s) {
@@ -562,9 +566,22 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
   // each x pass reads the factor table once (per RHS when each has its own)
   const double fb = (double)sizeof(T) * split_fac_elems(g.n) * (od.rhs_fac ? nrhs : 1);
   const cplx<T>* pc = reinterpret_cast<const cplx<T>*>(pin);
-  if (rdir && mode == SM_FWD_CGQF) {
-    // folded CG: r, q, p, x in; r, p, x and the x-transformed work spectrum
-    // out; then the new r.r
+  // the folded iteration (FWD_CGQF with rdir): the x inverse's partials (r.r,
+  // p.p) at the start of `partials`, then per RHS the z middle pass's sums
+  // (nzb) and the x forward's (2 nxb)
+  const bool fold = rdir && mode == SM_FWD_CGQF;
+  const int nzb = zpass_blocks(g.n, g.nrows, f64);
+  double* part_z = partials;
+  double* part_x = partials;
+  if (fold) {
+    const StrArgs<T> probe = split_x_args<T>(od, nullptr, work, nullptr, nullptr, st, skip, nullptr);
+    const int64_t nxb = probe.nblk0 + probe.nblk1;
+    if (nzb + 2 * nxb > partials_per_rhs(g)) return fail(WF_EINVAL, "partials too small");
+    part_x = partials + (int64_t)nrhs * nzb;
+  }
+  if (fold) {
+    // folded CG: r, q', p, x in; r, p, x and the x-transformed work spectrum
+    // out; then the new r.r and p.p
     StrArgs<T> xa = split_x_args<T>(od, reinterpret_cast<const cplx<T>*>(rdir), work, nullptr,
                                     nullptr, st, skip, partials);
     xa.s0.p = const_cast<cplx<T>*>(pc);
@@ -611,6 +628,7 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
     zm.tw = tw_of<T>(od);
     zm.st = st;
     zm.skip = skip;
+    zm.partials = fold ? part_z : nullptr;
     // spectrum in and out (in place), the noise diagonal in (once for all RHS
     // unless SD)
     ProfScope ps(od.prof, f64 ? WF_PROF_SZW_F64 : WF_PROF_SZW_F32,
@@ -623,19 +641,21 @@ Status split_passes(const OperatorData& od, int mode, const T* pin, cplx<T>* wor
   }
   const StrArgs<T> xa = split_x_args<T>(od, work, reinterpret_cast<cplx<T>*>(out), pc,
                                         reinterpret_cast<const cplx<double>*>(bh), st, skip,
-                                        partials);
+                                        fold ? part_x : partials);
   {
-    // work spectrum in, result out; CGQ also reads p, RES y and b (FP64)
+    // work spectrum in, result out; CGQ also reads p, RES y and b (FP64); the
+    // folded iteration's CGQF reads p at the monopole only
     double xb = 2 * sb + fb;
-    if (mode == SM_FWD_CGQ || mode == SM_FWD_CGQF) xb += sb;
+    if (mode == SM_FWD_CGQ) xb += sb;
     if (mode == SM_FWD_RES) xb += 2 * sb;
     ProfScope ps(od.prof, f64 ? WF_PROF_SXFWD_F64 : WF_PROF_SXFWD_F32, xb, s);
     WF_HIP(launch_strided<T>(g.n, mode, xa, nrhs, s));
   }
-  if (mode == SM_FWD_CGQ || mode == SM_FWD_RES || mode == SM_FWD_CGQF)
-    WF_HIP(launch_finalize(mode == SM_FWD_CGQ ? FIN_PQ : mode == SM_FWD_CGQF ? FIN_PQF : FIN_RES,
-                           partials, xa.nblk0 + xa.nblk1,
-                           skip, st, nrhs, s));
+  const int nxb = xa.nblk0 + xa.nblk1;
+  if (fold)
+    WF_HIP(launch_finalize_fold_pq(part_z, nzb, part_x, nxb, (double)g.m, skip, st, nrhs, s));
+  else if (mode == SM_FWD_CGQ || mode == SM_FWD_RES)
+    WF_HIP(launch_finalize(mode == SM_FWD_CGQ ? FIN_PQ : FIN_RES, partials, nxb, skip, st, nrhs, s));
   return {};
 }
 template Status split_passes<float>(const OperatorData&, int, const float*, cplx<float>*, float*,
@@ -835,11 +855,12 @@ Status run_lowpass(const Allocator& al, const OperatorData& od, DepositWork& dw,
 // it).  Split form, FP64: 152, a half spectrum being 8 B per cell: x inverse
 // with the direction update 48 (r, p, x in; p, x, work out), y 16, z middle
 // 24, y 16, x forward with q 24, r update 24.  Split form, FP32 (the folded
-// iteration): 72 -- x inverse with the r update and the direction 32 (r, q, p,
-// x in; r, p, x, work out), y 8, z middle 12, y 8, x forward with q 12.
+// iteration): 68 -- x inverse with the r update and the direction 32 (r, q',
+// p, x in; r, p, x, work out), y 8, z middle 12, y 8, x forward with q' 8
+// (work in, q' out).  The split x passes also read the factor table once.
 double model_bytes_iteration(bool fp64, bool split) {
   if (fp64) return 152.0;
-  return split ? 72.0 : 76.0;
+  return split ? 68.0 : 76.0;
 }
 // FP64 residual b - A x, also 104 in both forms (split: x inverse 16, y 16,
 // z middle 24, y 16, x forward with y and b in 32)

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(NT) void k_zinv(ZinvArgs<T> a) {
 // times the noise diagonal -> half spectrum, in place (the rows of a block are
 // its own)
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <typename T, int N, bool RED>
 __global__ __launch_bounds__(NT) void k_zmid(ZmidArgs<T> a) {
   using V = cplx<T>;
   using R = vec16<T>;
@@ -367,11 +367,13 @@ __global__ __launch_bounds__(NT) void k_zmid(ZmidArgs<T> a) {
   __syncthreads();
   fft_tile<T, N, NB, NT, false, +1>(lds, twl);
 
-  // real rows (re: r0, im: r0 + 1) times nbar w
+  // real rows (re: r0, im: r0 + 1) times nbar w; for the folded iteration
+  // also the block's sum of nbar w u^2 (its p.q' by Parseval)
   const T nbar = a.w_scaled ? T(1) : (T)st->nbar;
   const T* wr = a.w + rhs * a.rhs_w;
   constexpr int ITEMS3 = NB * N / RW;
   constexpr int PER3 = (ITEMS3 + NT - 1) / NT;
+  double wuu = 0.0;  // RED (the folded iteration): the block's sum of nbar w u^2
 #pragma unroll
   for (int c = 0; c < PER3; ++c) {
     const int q = threadIdx.x + c * NT;
@@ -382,9 +384,17 @@ __global__ __launch_bounds__(NT) void k_zmid(ZmidArgs<T> a) {
 #pragma unroll
       for (int j = 0; j < RW; ++j) {
         const V v = lds[b * N + z + j];
-        lds[b * N + z + j] = V{v.x * w0[j], v.y * w1[j]};
+        const V wv = V{v.x * w0[j], v.y * w1[j]};
+        lds[b * N + z + j] = wv;
+        // FP32 products (relative error 6e-8 each, unbiased), FP64 sums
+        if constexpr (RED) wuu += (double)(wv.x * v.x + wv.y * v.y);
       }
     }
+  }
+  if constexpr (RED) {
+    __shared__ double red[NT / 64];
+    const double part = block_sum(wuu, red);
+    if (threadIdx.x == 0) a.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = part;
   }
   __syncthreads();
   fft_tile<T, N, NB, NT, false, -1>(lds, twl);
@@ -497,10 +507,13 @@ __device__ __forceinline__ cplx<T> split_out(T f, int kz, bool dc, cplx<T> v, cp
                                             cplx<double> bv, double& acc, double& acc2) {
   f *= sqrt_d<T, N>(kz);
   cplx<T> o = {f * v.x, f * v.y};
-  if constexpr (MODE == SM_FWD_CGQ || MODE == SM_FWD_CGQF) {
+  if constexpr (MODE == SM_FWD_CGQ) {
     if (!dc) o = cadd(o, pv);
     acc += (double)pv.x * (double)o.x + (double)pv.y * (double)o.y;
-    if constexpr (MODE == SM_FWD_CGQF) acc2 += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+  } else if constexpr (MODE == SM_FWD_CGQF) {
+    // q' = c sqrt(D) v; pv is p at the monopole only (else zero)
+    acc += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+    acc2 += (double)pv.x * (double)o.x + (double)pv.y * (double)o.y;
   } else if constexpr (MODE == SM_FWD_RES) {
     if (!dc) o = cadd(o, pv);
     o = {(T)(bv.x - (double)o.x), (T)(bv.y - (double)o.y)};
@@ -586,9 +599,19 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
           }
         }
       }
-      // scaled (SCALE_IN) into the LDS tile
-      auto to_lds = [&](int c) {
+      // scaled (SCALE_IN) into the LDS tile.  INV_FOLD also sums |p|^2 of the
+      // group's reals from index pp_from on (0: all, 2: without the monopole;
+      // the default, one past the last, none) here, where the values are read
+      // anyway: summed in the direction loops, it made the pass spill
+      // registers under its 64-VGPR cap
+      double ppn = 0.0;
+      auto to_lds = [&](int c, int pp_from = 16 / (int)sizeof(T)) {
         const int q = threadIdx.x + c * NT;
+        if constexpr (MODE == SM_INV_FOLD) {
+#pragma unroll
+          for (int j = 0; j < 2 * CW; ++j)
+            if (j >= pp_from) ppn += (double)buf[c][j] * (double)buf[c][j];
+        }
         if constexpr (SCALE_IN) {
           const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
           T f[CW];
@@ -605,13 +628,17 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
         *reinterpret_cast<R*>(lds + q * CW) = buf[c];
       };
       if constexpr (MODE == SM_INV_FOLD) {
-        // folded CG step: `in` is r.  Pending (the previous iteration's
-        // alpha and beta): x += alpha p, r -= alpha q, p = r + beta p.  First
+        // folded CG step: `in` is r and `q` holds q', the noise part of the
+        // previous A p.  Pending (the previous iteration's alpha and beta):
+        // x += alpha p, r -= alpha ([m != 0] p + q'), p = r + beta p.  First
         // direction of a cycle: p = r.  Otherwise p is ready (a reliable
-        // update continued it).  Block partial of the new r.r.
+        // update continued it).  Block partials of the new r.r and of p.p
+        // without the monopole.
         const CgState* cs = a.st + rhs;
         const bool pending = cs->pending != 0, first = cs->first != 0;
         const T alpha = (T)cs->alpha, beta = (T)cs->beta;
+        // the monopole is element 0 of column 0, row 0, outer row 0 (main part)
+        const bool dc_tile = s.lam_kz < 0 && outer == 0 && b0 == 0;
         double rr = 0.0;
         if (pending) {
           // one element group at a time (few registers: two blocks per CU)
@@ -625,13 +652,19 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
               const R qv = ld16x<NTA>(reinterpret_cast<const T*>(s.q + vo));
               const R xv = ld16x<NTA>(reinterpret_cast<const T*>(s.x + vo));
               st16x<NTA>(reinterpret_cast<T*>(s.x + vo), xv + alpha * pv);
-              const R rn = buf[c] - alpha * qv;
+              R qe = qv + pv;
+              const bool dc0 = c == 0 && dc_tile && q == 0;  // (i, b) = (0, 0)
+              if (dc0) {
+                qe[0] = qv[0];
+                qe[1] = qv[1];
+              }
+              const R rn = buf[c] - alpha * qe;
               st16x<NTA>(reinterpret_cast<T*>(s.r + vo), rn);
 #pragma unroll
               for (int j = 0; j < 2 * CW; ++j) rr += (double)rn[j] * (double)rn[j];
               buf[c] = rn + beta * pv;
               st16x<NTA>(reinterpret_cast<T*>(s.p + vo), buf[c]);
-              to_lds(c);
+              to_lds(c, dc0 ? 2 : 0);
             }
           }
         } else {
@@ -646,12 +679,17 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
               T* pp = reinterpret_cast<T*>(s.p + vo);
               if (first) st16x<NTA>(pp, buf[c]);
               else buf[c] = ld16x<NTA>(pp);
-              to_lds(c);
+              const bool dc0 = c == 0 && dc_tile && q == 0;  // (i, b) = (0, 0)
+              to_lds(c, dc0 ? 2 : 0);
             }
           }
         }
         const double part = block_sum(rr, red);
-        if (threadIdx.x == 0) a.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = part;
+        const double part2 = block_sum(ppn, red);
+        if (threadIdx.x == 0) {
+          a.partials[(int64_t)rhs * 2 * gridDim.x + blockIdx.x] = part;
+          a.partials[((int64_t)rhs * 2 + 1) * gridDim.x + blockIdx.x] = part2;
+        }
       } else {
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
@@ -660,7 +698,7 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
         }
       }
     } else {
-      double rr_nv = 0.0;  // INV_FOLD: r.r of this thread
+      double rr_nv = 0.0, pp_nv = 0.0;  // INV_FOLD: r.r and p.p of this thread
       for (int e = threadIdx.x; e < TB * N; e += NT) {
         const int b = e % TB, i = e / TB;
         V v;
@@ -683,11 +721,13 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
         if constexpr (MODE == SM_INV_FOLD) {
           const CgState* cs = a.st + rhs;
           const int64_t o = rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i);
+          const bool dc = s.lam_kz < 0 && outer == 0 && b0 + b == 0 && i == 0;
           if (cs->pending) {
             const T al = (T)cs->alpha, be = (T)cs->beta;
             const V pv = s.p[o], qv = s.q[o], xv = s.x[o];
             s.x[o] = V{xv.x + al * pv.x, xv.y + al * pv.y};
-            v = V{v.x - al * qv.x, v.y - al * qv.y};
+            const V qe = dc ? qv : V{qv.x + pv.x, qv.y + pv.y};
+            v = V{v.x - al * qe.x, v.y - al * qe.y};
             s.r[o] = v;
             rr_nv += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
             v = V{v.x + be * pv.x, v.y + be * pv.y};
@@ -697,6 +737,7 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
             if (cs->first) s.p[o] = v;
             else v = s.p[o];
           }
+          if (!dc) pp_nv += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         }
         if constexpr (SCALE_IN) {
           T f;
@@ -710,7 +751,11 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
       }
       if constexpr (MODE == SM_INV_FOLD) {
         const double part = block_sum(rr_nv, red);
-        if (threadIdx.x == 0) a.partials[(int64_t)rhs * gridDim.x + blockIdx.x] = part;
+        const double part2 = block_sum(pp_nv, red);
+        if (threadIdx.x == 0) {
+          a.partials[(int64_t)rhs * 2 * gridDim.x + blockIdx.x] = part;
+          a.partials[((int64_t)rhs * 2 + 1) * gridDim.x + blockIdx.x] = part2;
+        }
       }
     }
   } else {
@@ -750,8 +795,10 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
   // short and other waves hide the loads, issued after the FFT).  Measured at
   // 512^3: the factors read here instead of after the FFT make the x forward
   // with q 7 % faster.
+  // (the folded iteration's x forward reads no aux vector)
   constexpr bool PRELOAD = REDUCE && VEC && NT <= 512;
-  R avp[PRELOAD ? PER : 1];
+  constexpr bool PRE_AUX = PRELOAD && MODE != SM_FWD_CGQF;
+  R avp[PRE_AUX ? PER : 1];
   T fpre[PRELOAD ? PER : 1][CW];
   if constexpr (PRELOAD) {
 #pragma unroll
@@ -759,8 +806,9 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
       const int q = threadIdx.x + c * NT;
       if (ITEMS % NT == 0 || q < ITEMS) {
         const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-        avp[c] = ld16x<NTA>(reinterpret_cast<const T*>(
-            s.aux + rhs * s.out_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i)));
+        if constexpr (PRE_AUX)
+          avp[c] = ld16x<NTA>(reinterpret_cast<const T*>(
+              s.aux + rhs * s.out_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i)));
         int kzp[CW];
         bool dcp[CW];
         split_facs<T, N, CW>(fac_r, s, outer, b0 + b, i, fpre[c], kzp, dcp);
@@ -847,15 +895,24 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
           const int64_t off = ob + vec_off<N>(outer, ncols, b0 + b, i);
           const R v = *reinterpret_cast<const R*>(lds + q * CW);
           R av{};
-          if constexpr (PRELOAD) {
+          if constexpr (PRE_AUX) {
             av = avp[c];
-          } else if constexpr (REDUCE) {
+          } else if constexpr (REDUCE && MODE != SM_FWD_CGQF) {
             av = ld16x<NTA>(reinterpret_cast<const T*>(s.aux + off));
           }
           T f[CW];
           int kz[CW];
           bool dc[CW];
           split_facs<T, N, CW>(fac_r, s, outer, b0 + b, i, f, kz, dc);
+          if constexpr (MODE == SM_FWD_CGQF) {
+#pragma unroll
+            for (int j = 0; j < CW; ++j)
+              if (dc[j]) {
+                const cplx<T> p0 = s.aux[off + j];
+                av[2 * j] = p0.x;
+                av[2 * j + 1] = p0.y;
+              }
+          }
           if constexpr (PRELOAD) {
 #pragma unroll
             for (int j = 0; j < CW; ++j) f[j] = fpre[c][j];  // (the loads above fold away)
@@ -881,7 +938,7 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
         int kz;
         bool dc;
         split_facs<T, N, 1>(fac_r, s, outer, b0 + b, i, &f, &kz, &dc);
-        const V pv = REDUCE ? s.aux[off] : V{T(0), T(0)};
+        const V pv = (REDUCE && (MODE != SM_FWD_CGQF || dc)) ? s.aux[off] : V{T(0), T(0)};
         cplx<double> bv{0.0, 0.0};
         if constexpr (MODE == SM_FWD_RES) bv = s.bvec[off];
         s.out[off] = split_out<T, N, MODE>(f, kz, dc, lds[e], pv, bv, acc, acc2);
@@ -993,28 +1050,21 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partials, int np
   const int rhs = blockIdx.x;
   CgState* st = st_all + rhs;
   if (skip_rhs(st, skip)) return;
-  if constexpr (KIND == FIN_PQF) {
+  if constexpr (KIND == FIN_RRF) {
+    // after INV_FOLD: the new r.r and p.p (two regions); when the pass
+    // applied the previous step, one iteration more
     const double* p = partials + (int64_t)rhs * 2 * nparts;
-    const double pq = sum_parts(p, nparts, red);
-    const double qq = sum_parts(p + nparts, nparts, red);
+    const double tot = sum_parts(p, nparts, red);
+    const double ppn = sum_parts(p + nparts, nparts, red);
     if (threadIdx.x != 0) return;
-    st->pq = pq;
-    if (!(pq > 0.0) || !isfinite(pq)) {
-      st->done = 1;
-      st->status = CG_BREAKDOWN;
-      st->pending = 0;
-      return;
+    if (st->pending) {
+      count_iteration(st, tot);
+      st->rho_old = st->rho;
     }
-    // alpha from the exact r.r; the next r.r for beta before r itself is
-    // updated: |r - alpha q|^2 = r.r - 2 alpha r.q + alpha^2 q.q, with r.q =
-    // p.q (r and p differ by a multiple of the previous direction, which is
-    // conjugate to p), that is alpha^2 q.q - r.r.  A negative value (total
-    // cancellation) restarts the direction.
-    const double alpha = st->rho / pq;
-    const double rho_next = alpha * alpha * qq - st->rho;
-    st->alpha = alpha;
-    st->beta = rho_next > 0.0 ? rho_next / st->rho : 0.0;
-    st->pending = 1;
+    st->rho = tot;
+    st->pp = ppn;
+    st->first = 0;
+    st->pending = 0;
     return;
   } else {
     const double tot = sum_parts(partials + (int64_t)rhs * nparts, nparts, red);
@@ -1035,19 +1085,58 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partials, int np
       st->rho = tot;
       st->first = 0;
       st->pending = 1;
-    } else if constexpr (KIND == FIN_RRF) {
-      // after INV_FOLD: when it applied the previous step, one iteration more
-      if (st->pending) {
-        count_iteration(st, tot);
-        st->rho_old = st->rho;
-      }
-      st->rho = tot;
-      st->first = 0;
-      st->pending = 0;
     } else {  // FIN_RES
       st->outer_rr = tot;
     }
   }
+}
+
+// Folded iteration, after FWD_CGQF: p.q and q.q from p.p (FIN_RRF), the z
+// middle pass's sums of nbar w u^2 and FWD_CGQF's q'.q' and monopole term;
+// alpha, and beta from the recurrence.
+__global__ __launch_bounds__(256) void k_finalize_fold_pq(const double* part_z, int nzb,
+                                                          const double* part_x, int nxb,
+                                                          double m_cells, int skip,
+                                                          CgState* st_all) {
+  __shared__ double red[4];
+  const int rhs = blockIdx.x;
+  CgState* st = st_all + rhs;
+  if (skip_rhs(st, skip)) return;
+  const double wuu = sum_parts(part_z + (int64_t)rhs * nzb, nzb, red);
+  const double* px = part_x + (int64_t)rhs * 2 * nxb;
+  const double qnqn = sum_parts(px, nxb, red);
+  const double p0q0 = sum_parts(px + nxb, nxb, red);
+  if (threadIdx.x != 0) return;
+  // q = [m != 0] p + q' with p.q' = M sum(nbar w u^2) (Parseval: q' is
+  // C diag(nbar w) C p in the half-spectrum inner product)
+  const double pqn = m_cells * wuu;
+  const double pq = st->pp + pqn;
+  const double qq = st->pp + 2.0 * (pqn - p0q0) + qnqn;
+  st->pq = pq;
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    st->done = 1;
+    st->status = CG_BREAKDOWN;
+    st->pending = 0;
+    return;
+  }
+  // alpha from the exact r.r; the next r.r for beta before r itself is
+  // updated: |r - alpha q|^2 = r.r - 2 alpha r.q + alpha^2 q.q, with r.q =
+  // p.q (r and p differ by a multiple of the previous direction, which is
+  // conjugate to p), that is alpha^2 q.q - r.r.  A negative value (total
+  // cancellation) restarts the direction.
+  const double alpha = st->rho / pq;
+  const double rho_next = alpha * alpha * qq - st->rho;
+  st->alpha = alpha;
+  st->beta = rho_next > 0.0 ? rho_next / st->rho : 0.0;
+  st->pending = 1;
+}
+
+hipError_t launch_finalize_fold_pq(const double* part_z, int nzb, const double* part_x, int nxb,
+                                   double m_cells, int skip, CgState* st, int nrhs,
+                                   hipStream_t s) {
+  klaunch(k_finalize_fold_pq, dim3(nrhs), dim3(256), 0, s, part_z, nzb, part_x, nxb, m_cells, skip,
+          st);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(int kind, const double* partials, int nparts, int skip, CgState* st,
@@ -1061,9 +1150,6 @@ hipError_t launch_finalize(int kind, const double* partials, int nparts, int ski
       break;
     case FIN_RES:
       klaunch(k_finalize<FIN_RES>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
-      break;
-    case FIN_PQF:
-      klaunch(k_finalize<FIN_PQF>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
       break;
     case FIN_RRF:
       klaunch(k_finalize<FIN_RRF>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
@@ -1249,7 +1335,15 @@ template <typename T, int N>
 static hipError_t zmid_n(const ZmidArgs<T>& a, int64_t nrows, int nrhs, hipStream_t s) {
   constexpr int NB = z_nb<T, N>();
   dim3 grid((unsigned)(nrows / (2 * NB)), (unsigned)nrhs);
-  klaunch((k_zmid<T, N>), grid, dim3(NT), 0, s, a);
+  if constexpr (sizeof(T) == 4) {
+    if (a.partials) {
+      klaunch((k_zmid<T, N, true>), grid, dim3(NT), 0, s, a);
+      return hipGetLastError();
+    }
+  } else {
+    if (a.partials) return hipErrorInvalidValue;  // the folded iteration is FP32 only
+  }
+  klaunch((k_zmid<T, N, false>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 

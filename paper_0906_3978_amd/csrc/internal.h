@@ -167,6 +167,8 @@ struct SolveWork {
   Status pull_state(hipStream_t s);
 };
 
+// doubles of block partials a solve keeps per RHS
+int64_t partials_per_rhs(const Grid& g);
 Status make_twiddles(const Allocator& al, int n, DevBuf& tw64, DevBuf* tw32, hipStream_t s);
 // Prior-split operator (C A C) on half-spectrum vectors (stride spec_total
 // complex per RHS).  ensure_split_fac builds c once per power spectrum.

@@ -81,6 +81,8 @@ template <typename T> struct ZmidArgs {
   const cplx<T>* tw;
   const CgState* st;        // required
   int32_t skip;             // SKIP_*
+  double* partials;         // folded FP32 iteration: per RHS and block, the sum of
+                            // nbar w u^2 over the block's real field u (else null)
 };
 
 // ---- strided passes (y or x axis), tiles of TB neighbouring pencils -------
@@ -95,8 +97,11 @@ template <typename T> struct ZmidArgs {
 // INV_DIR is INV_SCALE of the CG direction, formed on the way in: `in` is r,
 // the pending x += alpha p is applied and p = r + beta p written back (Seg p, x).
 // INV_FOLD (FP32 prior-split CG) also applies the pending r -= alpha q (Seg r,
-// q) before the direction and writes the block partials of the new r.r;
-// FWD_CGQF is FWD_CGQ that also sums q.q (two partials per block).
+// q) before the direction and writes the block partials of the new r.r and
+// of p.p without the monopole.  Its q holds only the noise part of C A C p,
+// q' = c sqrt(D) v: FWD_CGQF writes q' and the block partials of q'.q' and of
+// p(0) q'(0) (the monopole's term, nonzero in one block), and reads p for the
+// monopole only; INV_FOLD applies r -= alpha ([m != 0] p + q').
 enum StrMode : int {
   SM_FWD = 0, SM_INV = 1, SM_FWD_LAM_INV = 2, SM_FWD_CROP = 3,
   SM_INV_SCALE = 4, SM_FWD_SCALE = 5, SM_FWD_CGQ = 6, SM_FWD_RES = 7, SM_INV_DIR = 8,
@@ -130,8 +135,9 @@ template <typename T> struct StrArgs {
   const T* fac;             // split modes: c over (|my|, |mx|, kz), in blocks of 16 kz:
                             // [|my|][kz / 16][|mx|][kz % 16]
   double in_scale;          // SM_INV_SCALE: 1 / M
-  double* partials;         // SM_FWD_CGQ / SM_FWD_RES / SM_INV_FOLD: per RHS, one per
-                            // block; SM_FWD_CGQF: per RHS, p.q of every block, then q.q
+  double* partials;         // SM_FWD_CGQ / SM_FWD_RES: per RHS, one per block;
+                            // SM_INV_FOLD: per RHS, r.r of every block, then p.p;
+                            // SM_FWD_CGQF: per RHS, q'.q' of every block, then p(0) q'(0)
   int64_t rhs_lam, rhs_fac; // per-RHS strides of lam and fac (0: shared)
 };
 
@@ -153,11 +159,17 @@ template <typename T> hipError_t launch_zmid(int n, const ZmidArgs<T>& a, int64_
 // updates the CG state: FIN_PQ -> alpha (or breakdown), FIN_RR -> iteration
 // bookkeeping, beta and stopping, FIN_RES -> outer_rr.  The folded FP32
 // prior-split iteration uses FIN_RRF after INV_FOLD (the new r.r: iteration
-// bookkeeping and stopping) and FIN_PQF after FWD_CGQF (alpha, and beta from
-// r.r - 2 alpha p.q + alpha^2 q.q with p.q standing in for r.q).
-enum FinKind : int { FIN_PQ = 0, FIN_RR = 1, FIN_RES = 2, FIN_PQF = 3, FIN_RRF = 4 };
+// bookkeeping and stopping; p.p) and, after FWD_CGQF, launch_finalize_fold_pq.
+enum FinKind : int { FIN_PQ = 0, FIN_RR = 1, FIN_RES = 2, FIN_RRF = 4 };
 hipError_t launch_finalize(int kind, const double* partials, int nparts, int skip, CgState* st,
                            int nrhs, hipStream_t s);
+// Folded iteration, after FWD_CGQF: p.q = p.p + M sum(nbar w u^2) (the noise
+// part by Parseval, from the z middle pass's partials: nzb per RHS), q.q =
+// p.p + 2 (M sum(nbar w u^2) - p(0) q'(0)) + q'.q' (from FWD_CGQF's: 2 nxb
+// per RHS); alpha, and beta from r.r - 2 alpha p.q + alpha^2 q.q with p.q
+// standing in for r.q.
+hipError_t launch_finalize_fold_pq(const double* part_z, int nzb, const double* part_x, int nxb,
+                                   double m_cells, int skip, CgState* st, int nrhs, hipStream_t s);
 
 // ---- vector kernels --------------------------------------------------------
 constexpr int VEC_THREADS = 256;

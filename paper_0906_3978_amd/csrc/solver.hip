@@ -75,10 +75,13 @@ Status cg_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hi
 // One CG iteration of the prior-split system; vectors are half spectra.
 // FP32 (the inner iteration of mixed solves) folds the residual update into
 // the first pass of the next iteration: the x pass that forms the direction
-// also applies r -= alpha q, and beta comes from p.q and q.q (see FIN_PQF),
-// which saves the separate update kernel's sweep over r and q.  The
-// iteration in which a reliable update falls due has already formed its
-// direction; the update continues that direction (see k_rel_reset).
+// also applies r -= alpha q, and beta comes from p.q and q.q (see
+// launch_finalize_fold_pq), which saves the separate update kernel's sweep
+// over r and q.  Its q vector keeps only the noise part of C A C p, so that
+// the x forward pass need not read p: p.q follows from p.p and, by Parseval,
+// from the z middle pass's sum of nbar w u^2.  The iteration in which a
+// reliable update falls due has already formed its direction; the update
+// continues that direction (see k_rel_reset).
 template <typename T>
 Status split_iteration(const OperatorData& od, SolveWork& sw, Vecs<T> v, int nr, hipStream_t s) {
   CgState* st = sw.state.as<CgState>();
@@ -419,7 +422,7 @@ struct SnapHeader {
   int32_t mixed;  // 1: mixed precision (FP64 x, r; FP32 x, r, p and, prior-split, q)
   int32_t pad;
 };
-constexpr uint64_t SNAP_MAGIC = 0x5746534e41503033ull;  // "WFSNAP03"
+constexpr uint64_t SNAP_MAGIC = 0x5746534e41503034ull;  // "WFSNAP04"
 }  // namespace
 
 static size_t vector_len(const Grid& g, bool split) {
