@@ -150,3 +150,32 @@ def test_folded_cg_converges_like_textbook():
         if k < ref["iterations"]:
             assert rel > 1e-10 * 0.5
     assert rel <= 2e-10
+
+
+def test_noise_part_decomposition():
+    """The folded iteration keeps q' = C (nbar W) C p and forms the rest of
+    q = (C A C) p from p itself: q = (I - P0) p + q' (P0 the monopole
+    projection; Lambda_0 = 0 for the flat monopole prior), p.q' = nbar
+    sum(w (C p)^2) (what the z middle pass sums, up to the transform's
+    normalisation), and p.q, q.q from p.p without the monopole, p.q', q'.q'
+    and the monopole's p(0) q'(0) -- written out on the oracle's real-space
+    prior-split system."""
+    sp, _ = _split_problem(n=8, nbar=7.0)
+    base = sp.base
+    rng = np.random.Generator(np.random.PCG64(21))
+    p = rng.standard_normal((8,) * 3)
+    q = sp.apply(p)
+    cp = sp.split(p)
+    qn = sp.split(base.nw * cp)
+    p_nm = p - p.mean()                       # (I - P0) p
+    assert np.allclose(q, p_nm + qn, rtol=0, atol=1e-12 * np.abs(q).max())
+    pqn = float(np.vdot(p, qn))
+    assert abs(pqn / float(np.sum(base.nw * cp * cp)) - 1.0) < 1e-12
+    # in the Fourier basis: the monopole term is the mean's
+    m = p.size
+    p0q0 = m * p.mean() * qn.mean()           # p(0) q'(0) / M for numpy's unnormalised DFT
+    pp = float(np.vdot(p_nm, p_nm))
+    pq = pp + pqn
+    qq = pp + 2.0 * (pqn - p0q0) + float(np.vdot(qn, qn))
+    assert abs(pq / float(np.vdot(p, q)) - 1.0) < 1e-12
+    assert abs(qq / float(np.vdot(q, q)) - 1.0) < 1e-12
