@@ -608,9 +608,11 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
       auto to_lds = [&](int c, int pp_from = 16 / (int)sizeof(T)) {
         const int q = threadIdx.x + c * NT;
         if constexpr (MODE == SM_INV_FOLD) {
+          T sq = T(0);  // (FP32 over the group's four values: fewer registers)
 #pragma unroll
           for (int j = 0; j < 2 * CW; ++j)
-            if (j >= pp_from) ppn += (double)buf[c][j] * (double)buf[c][j];
+            if (j >= pp_from) sq += buf[c][j] * buf[c][j];
+          ppn += (double)sq;
         }
         if constexpr (SCALE_IN) {
           const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
