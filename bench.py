@@ -11,8 +11,9 @@ Prints one JSON line: solves/s, the roofline figure of the dominant kernel
 (HIP events around its launches during the timed steps), the error against
 the oracle's stored reference solution, the FP64 and plain-CG comparisons, the
 oracle timed on the host cores, the post-solve functions, and (each can be
-switched off with 0) a 16-RHS batch at 256^3, a serving stream and 200
-signal-dependent-noise jackknife solves at 128^3.
+switched off with 0) a 16-RHS batch at 256^3, a serving stream, 200
+signal-dependent-noise jackknife solves at 128^3 and the deposit of 2e6
+galaxies from spread out to piled on one point.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -563,6 +564,60 @@ def sd_run(nsamples, precond="prior", tol=1e-6):
     return res
 
 
+def deposit_run(n_gal, reps=5, seed=9100):
+    """Deposit under contention (Sec. 3.1.2 mass assignment, int64 atomics):
+    n_gal galaxies spread in four ways, from none to all on one point, on the
+    serving mix's 128^3 grid (CIC, 2x supersampled: 256^3 fine nodes) and the
+    headline 512^3 grid (TSC, 2x: 1024^3).  The time is the deposit class of
+    the profiler (zero-fill of the fine grid + the atomic deposit); the empty
+    catalogue gives the fill alone, so the difference is what the atomics
+    cost.  Spreads: `uniform` in the box; `lognormal`, the BBKS lognormal-
+    Poisson field of the grid (full sky); `blob`, a Gaussian of one fine cell's
+    width around the box centre; `point`, every galaxy at one position (each
+    of its 8 or 27 fine nodes takes n_gal atomic adds)."""
+    import synth
+    import torch
+    import paper_0906_3978_amd as wf
+    dev = torch.device("cuda:0")
+    out = {}
+    for n, scheme, box in ((128, "cic", 500.0), (512, "tsc", 500.0)):
+        nf = 2 * n
+        ptab = synth.p_by_m2(lambda k: synth.bbks_power(k), n, box)
+        w = np.ones((n, n, n))
+        rng = np.random.Generator(np.random.PCG64(seed + n))
+        centre = 0.5 * box + 0.3 * box / nf
+        blob = np.mod(centre + rng.normal(0.0, box / nf, size=(n_gal, 3)), box)
+        blob[blob >= box] = 0.0
+        cats = {"empty": np.zeros((0, 3)),
+                "uniform": synth.uniform_catalogue(n_gal, box, seed + 1),
+                "lognormal": synth.lognormal_catalogue(ptab, w, box, n_gal, seed + 2).xyz,
+                "blob": np.ascontiguousarray(blob),
+                "point": np.full((n_gal, 3), centre)}
+        ctx = wf.Context(0)
+        ctx.set_grid(n, box)
+        ctx.set_mask(torch.from_numpy(w).to(dev))
+        ctx.set_power(torch.from_numpy(ptab).to(dev))
+        row = {}
+        for name, xyz in cats.items():
+            ctx.set_galaxies(torch.from_numpy(xyz).to(dev) if len(xyz) else xyz)
+            ctx.deposit(scheme, 2)
+            ctx.profile_enable(True)
+            for _ in range(reps):
+                ctx.deposit(scheme, 2)
+            prof = ctx.profile_read()["deposit"]
+            ctx.profile_enable(False)
+            row[name] = {"n_gal": int(len(xyz)), "ms": round(prof["ms"] / prof["launches"], 4)}
+        fill = row["empty"]["ms"]
+        for name, r in row.items():
+            if r["n_gal"]:
+                r["atomics_ms"] = round(r["ms"] - fill, 4)
+                r["ns_per_galaxy"] = round(1e6 * (r["ms"] - fill) / r["n_gal"], 3)
+        out[f"{n}^3 {scheme} 2x"] = row
+        log(f"[deposit] {n}^3 {scheme}: " + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in row.items()))
+        ctx.close()
+    return out
+
+
 def traffic_for(kernel, launch_bytes):
     """HBM bytes per launch from committed rocprofv3 PMC counters, if they were
     taken on the current kernel sources."""
@@ -613,6 +668,9 @@ def main():
     ap.add_argument("--configs", type=int, default=1,
                     help="also run the plain FP64 configurations (32^3 power law, 256^3 BBKS) "
                          "with the oracle beside them (0: skip)")
+    ap.add_argument("--deposit-stress", type=int, default=2_000_000,
+                    help="also time the deposit of this many galaxies spread uniformly, "
+                         "clustered and piled on one point, at 128^3 and 512^3 (0: skip)")
     ap.add_argument("--batch", type=int, default=16,
                     help="also run the multi-RHS batch: this many 256^3 catalogues in one solve "
                          "(0: skip)")
@@ -791,6 +849,7 @@ def main():
     serving = serve(args.serve, args.tol, args.precond) if args.serve else None
     batch = batch_run(args.batch, args.tol, args.precond) if args.batch else None
     sdres = sd_run(args.sd, args.precond) if args.sd else None
+    dep = deposit_run(args.deposit_stress) if args.deposit_stress else None
 
     lat_ms = sorted(1e3 * x for x in lat)
     res = {
@@ -832,6 +891,7 @@ def main():
         "serving": serving,
         "batch": batch,
         "signal_dependent": sdres,
+        "deposit_contention": dep,
     }
     print(json.dumps(res))
 

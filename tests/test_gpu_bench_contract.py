@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_bench_json_contract():
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--n", "64", "--steps", "2",
            "--warmup", "1", "--serve", "0", "--batch", "0", "--sd", "0", "--no-post",
-           "--configs", "0"]
+           "--configs", "0", "--deposit-stress", "0"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=200, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     d = json.loads(r.stdout.strip().splitlines()[-1])
