@@ -1284,6 +1284,16 @@ int strided_tb(int n, bool fp64) {
   }
 }
 
+int split_vec_tile(int n) {
+  switch (n) {
+#define X(L) \
+  case L: return vec_tile<L>();
+    WF_FOR_LENGTHS(X)
+#undef X
+    default: return 0;
+  }
+}
+
 int zpass_nb(int n, bool fp64) {
   switch (n) {
 #define X(L) \

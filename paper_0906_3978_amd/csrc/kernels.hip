@@ -277,24 +277,31 @@ hipError_t launch_rel_init(double* x64, double* r64, const double* b, float* x32
   return hipGetLastError();
 }
 
-// Weight of element i (a double of an interleaved half spectrum: main
-// [x][y][kz < n/2] then the kz = n/2 plane [x][y]) in ||C v||^2: the square
-// of the prior-split factor of its mode.
-__device__ __forceinline__ double split_weight(const double* fac, int n, int64_t spec_main,
-                                              int64_t i) {
+// Weight of element i (a double of an interleaved half spectrum of the
+// prior-split form) in ||C v||^2: the square of the prior-split factor of its
+// mode.  Those vectors are stored in the x pass's tile order with tiles of tv
+// columns: the main part holds column kz of outer row y at x index x at
+// ((y (h / tv) + kz / tv) n + x) tv + kz % tv, the kz = h plane that follows
+// it holds column y at ((y / tv) n + x) tv + y % tv (h = n / 2).
+__device__ __forceinline__ double split_weight(const double* fac, int n, int tv,
+                                              int64_t spec_main, int64_t i) {
   const int64_t ci = i >> 1;
   const int h = n / 2;
   int x, y, kz;
   if (ci < spec_main) {
-    kz = (int)(ci % h);
-    const int64_t row = ci / h;
-    y = (int)(row % n);
-    x = (int)(row / n);
+    const int64_t t = ci / tv;  // (y (h / tv) + kz / tv) n + x
+    const int64_t u = t / n;    // y (h / tv) + kz / tv
+    const int nb = h / tv;
+    x = (int)(t - u * n);
+    y = (int)(u / nb);
+    kz = (int)(u - (int64_t)y * nb) * tv + (int)(ci - t * tv);
   } else {
     const int64_t cj = ci - spec_main;
+    const int64_t t = cj / tv;  // (y / tv) n + x
+    const int64_t u = t / n;
+    x = (int)(t - u * n);
+    y = (int)u * tv + (int)(cj - t * tv);
     kz = h;
-    y = (int)(cj % n);
-    x = (int)(cj / n);
   }
   const int mx = x <= h ? x : n - x, my = y <= h ? y : n - y;
   const int kzb = (h + SPLIT_FB) / SPLIT_FB;
@@ -309,7 +316,7 @@ __device__ __forceinline__ double split_weight(const double* fac, int n, int64_t
 // norms are those of s = C y).
 __global__ __launch_bounds__(VEC_THREADS) void k_rel_fold(double* x64, float* x32, const float* p32,
                                                           int64_t m, int64_t rs, double* partials,
-                                                          const double* fac, int n,
+                                                          const double* fac, int n, int tv,
                                                           int64_t spec_main, int64_t fac_rs,
                                                           CgState* st_all) {
   __shared__ double red[VEC_THREADS / 64];
@@ -327,7 +334,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_rel_fold(double* x64, float* x3
     const double xn = x64[o + i] + d;
     x64[o + i] = xn;
     x32[o + i] = 0.f;
-    const double wgt = fr ? split_weight(fr, n, spec_main, i) : 1.0;
+    const double wgt = fr ? split_weight(fr, n, tv, spec_main, i) : 1.0;
     dd += wgt * d * d;
     xx += wgt * xn * xn;
   }
@@ -348,8 +355,9 @@ hipError_t launch_rel_fold(double* x64, float* x32, const float* p32, int64_t m,
                            double* partials, const double* fac, int n, int64_t spec_main,
                            int64_t fac_rs, CgState* st, int nrhs, hipStream_t s) {
   dim3 grid(vec_blocks(m), nrhs);
+  const int tv = fac ? split_vec_tile(n) : 1;
   klaunch(k_rel_fold, grid, dim3(VEC_THREADS), 0, s, x64, x32, p32, m, rs, partials,
-                     fac, n, spec_main, fac_rs, st);
+                     fac, n, tv, spec_main, fac_rs, st);
   return hipGetLastError();
 }
 

@@ -142,6 +142,7 @@ template <typename T> struct StrArgs {
 };
 
 int strided_tb(int n, bool fp64);   // batch width of a strided tile
+int split_vec_tile(int n);          // tile width of the prior-split vectors' layout
 int zpass_nb(int n, bool fp64);     // pencils (row pairs) per z-pass block
 int zpass_blocks(int n, int64_t nrows, bool fp64);  // blocks of one z-pass launch
 bool fft_length_supported(int n, bool fp64);

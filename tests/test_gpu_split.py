@@ -116,6 +116,34 @@ def test_split_mixed(ctx, bbks48, tol):
     assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("precond", ["prior", "none"])
+def test_mixed_last_change_is_the_change_of_s(ctx, bbks48, precond):
+    """The change a reliable update reports (last_change, what the settle rule
+    sums) is ||s_k+1 - s_k|| / ||s_k+1|| of the solutions the same mixed solve
+    returns when it is stopped after k and after k + 1 updates (the two runs
+    agree bit for bit up to the k-th).  The prior-split form measures it on
+    the half spectrum of y, each mode weighted by its factor squared: this
+    pins that weighting to the modes' places in the vectors' tile layout (the
+    weights of the [x][y][kz] order instead, which the vectors do not use,
+    put the value several per cent off here).  The bound: in the kz = 0 and N/2
+    planes the half spectrum stores both members of each conjugate pair, and
+    the FP32 iteration leaves them conjugate only to rounding; that part has
+    no real-space counterpart and adds ~(1e-7 ||y|| / ||change||)^2 / 2 to the
+    reported value, 3e-7 of it for a change of 1e-4 (measured at update 5)."""
+    _load(ctx, bbks48)
+    kw = dict(precision="mixed", precond=precond, tol=1e-14, max_iter=100000, err_tol=-1.0,
+              allow=(WF_ENOTCONV,))
+    for k in (2, 4):
+        xa, ia = ctx.solve(max_outer=k, **kw)
+        xb, ib = ctx.solve(max_outer=k + 1, **kw)
+        assert ib.outer_steps == ia.outer_steps + 1 and ib.iters_total > ia.iters_total
+        change = float(np.linalg.norm(xb - xa) / np.linalg.norm(xb))
+        print(f"{precond} update {k + 1}: reported {ib.last_change:.6e}, "
+              f"from the solutions {change:.6e}")
+        assert 1e-8 < change < 1.0
+        assert abs(ib.last_change / change - 1.0) < 1e-5
+
+
 def test_split_zero_rhs(ctx, bbks48):
     d = bbks48
     wl = d["wl"]
