@@ -130,7 +130,10 @@ typedef struct wf_server wf_server;
  *               of the operator, which grows with nbar, leaves large-scale
  *               error in the unobserved region that the residual barely
  *               weights until it has dropped further; that error shows in the
- *               change the following FP64 refresh makes. */
+ *               change the following FP64 refresh makes.  An error that stays
+ *               put between refreshes does not: at extreme densities in small
+ *               caps (nbar ~ 800 in a 30 degree cap) a uniform offset of the
+ *               unobserved volume of ~1e-6 can remain; FP64 has no such floor. */
 typedef struct {
   wf_precision precision;
   double tol;
