@@ -447,6 +447,26 @@ __device__ __forceinline__ int64_t vec_off(int outer, int ncols, int c, int i) {
   return ((int64_t)(outer * (ncols / TV) + c / TV) * N + i) * TV + c % TV;
 }
 
+// vec_off as a block's base (columns from c0, a multiple of the layout's tile
+// width: the same for every thread) plus the byte offset of column c0 + c, x
+// index i from there (below 2^31 for any grid), so that loads and stores can
+// take the base from scalar registers and one 32-bit offset per thread.
+template <int N>
+__device__ __forceinline__ int64_t vec_base(int outer, int ncols, int c0) {
+  constexpr int TV = vec_tile<N>();
+  return (int64_t)(outer * (ncols / TV) + c0 / TV) * N * TV;
+}
+template <typename T, int N> __device__ __forceinline__ uint32_t vec_in_bytes(int c, int i) {
+  constexpr int TV = vec_tile<N>();
+  return (uint32_t)((((c / TV) * N + i) * TV + c % TV) * (int)sizeof(cplx<T>));
+}
+template <typename T> __device__ __forceinline__ T* at_bytes(T* base, uint32_t bytes) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + bytes);
+}
+template <typename T> __device__ __forceinline__ const T* at_bytes(const T* base, uint32_t bytes) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + bytes);
+}
+
 // Prior-split factor table: c over (|my|, |mx|, kz) in [0, N/2]^3, stored in
 // blocks of FB consecutive kz: [|my|][kz / FB][|mx|][kz % FB].  An x-pass
 // tile (one |my|, up to FB consecutive kz, every x) then reads one
@@ -569,8 +589,9 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
         if (ITEMS % NT == 0 || q < ITEMS) {
           const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
           if constexpr (SCALE_IN)
-            buf[c] = ld16x<NTA>(reinterpret_cast<const T*>(
-                s.in + rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i)));
+            buf[c] = ld16x<NTA>(at_bytes(reinterpret_cast<const T*>(
+                s.in + rhs * s.in_rhs + vec_base<N>(outer, s.n_btiles * TB, b0)),
+                vec_in_bytes<T, N>(b, i)));
           else
             buf[c] = ld16x<NTA>(reinterpret_cast<const T*>(in + i * s.in_axis + b));
         }
@@ -580,17 +601,20 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
         const CgState* cs = a.st + rhs;
         const bool first = cs->first != 0, pending = cs->pending != 0;
         const T alpha = (T)cs->alpha, beta = (T)cs->beta;
+        const int64_t vb = rhs * s.in_rhs + vec_base<N>(outer, s.n_btiles * TB, b0);
+        T* pb = reinterpret_cast<T*>(s.p + vb);
+        T* xb = reinterpret_cast<T*>(s.x + vb);
 #pragma unroll
         for (int c = 0; c < PER; ++c) {
           const int q = threadIdx.x + c * NT;
           if (ITEMS % NT == 0 || q < ITEMS) {
             const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-            const int64_t vo = rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i);
-            T* pp = reinterpret_cast<T*>(s.p + vo);
+            const uint32_t vo = vec_in_bytes<T, N>(b, i);
+            T* pp = at_bytes(pb, vo);
             if (!first) {
               const R pv = ld16x<NTA>(pp);
               if (pending) {
-                T* xp = reinterpret_cast<T*>(s.x + vo);
+                T* xp = at_bytes(xb, vo);
                 st16x<NTA>(xp, ld16x<NTA>(xp) + alpha * pv);
               }
               buf[c] += beta * pv;
@@ -641,6 +665,11 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
         const T alpha = (T)cs->alpha, beta = (T)cs->beta;
         // the monopole is element 0 of column 0, row 0, outer row 0 (main part)
         const bool dc_tile = s.lam_kz < 0 && outer == 0 && b0 == 0;
+        const int64_t vb = rhs * s.in_rhs + vec_base<N>(outer, s.n_btiles * TB, b0);
+        T* pb = reinterpret_cast<T*>(s.p + vb);
+        T* xb = reinterpret_cast<T*>(s.x + vb);
+        T* rb = reinterpret_cast<T*>(s.r + vb);
+        const T* qb = reinterpret_cast<const T*>(s.q + vb);
         double rr = 0.0;
         if (pending) {
           // one element group at a time (few registers: two blocks per CU)
@@ -649,11 +678,11 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
             const int q = threadIdx.x + c * NT;
             if (ITEMS % NT == 0 || q < ITEMS) {
               const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-              const int64_t vo = rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i);
-              const R pv = ld16x<NTA>(reinterpret_cast<const T*>(s.p + vo));
-              const R qv = ld16x<NTA>(reinterpret_cast<const T*>(s.q + vo));
-              const R xv = ld16x<NTA>(reinterpret_cast<const T*>(s.x + vo));
-              st16x<NTA>(reinterpret_cast<T*>(s.x + vo), xv + alpha * pv);
+              const uint32_t vo = vec_in_bytes<T, N>(b, i);
+              const R pv = ld16x<NTA>(at_bytes(pb, vo));
+              const R qv = ld16x<NTA>(at_bytes(qb, vo));
+              const R xv = ld16x<NTA>(at_bytes(xb, vo));
+              st16x<NTA>(at_bytes(xb, vo), xv + alpha * pv);
               R qe = qv + pv;
               const bool dc0 = c == 0 && dc_tile && q == 0;  // (i, b) = (0, 0)
               if (dc0) {
@@ -661,11 +690,11 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
                 qe[1] = qv[1];
               }
               const R rn = buf[c] - alpha * qe;
-              st16x<NTA>(reinterpret_cast<T*>(s.r + vo), rn);
+              st16x<NTA>(at_bytes(rb, vo), rn);
 #pragma unroll
               for (int j = 0; j < 2 * CW; ++j) rr += (double)rn[j] * (double)rn[j];
               buf[c] = rn + beta * pv;
-              st16x<NTA>(reinterpret_cast<T*>(s.p + vo), buf[c]);
+              st16x<NTA>(at_bytes(pb, vo), buf[c]);
               to_lds(c, dc0 ? 2 : 0);
             }
           }
@@ -675,10 +704,9 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
             const int q = threadIdx.x + c * NT;
             if (ITEMS % NT == 0 || q < ITEMS) {
               const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-              const int64_t vo = rhs * s.in_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i);
 #pragma unroll
               for (int j = 0; j < 2 * CW; ++j) rr += (double)buf[c][j] * (double)buf[c][j];
-              T* pp = reinterpret_cast<T*>(s.p + vo);
+              T* pp = at_bytes(pb, vec_in_bytes<T, N>(b, i));
               if (first) st16x<NTA>(pp, buf[c]);
               else buf[c] = ld16x<NTA>(pp);
               const bool dc0 = c == 0 && dc_tile && q == 0;  // (i, b) = (0, 0)
@@ -800,6 +828,9 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
   // (the folded iteration's x forward reads no aux vector)
   constexpr bool PRELOAD = REDUCE && VEC && NT <= 512;
   constexpr bool PRE_AUX = PRELOAD && MODE != SM_FWD_CGQF;
+  // the split output's tile in the vector layout, and the aux vector's
+  const int64_t vb_out = rhs * s.out_rhs + vec_base<N>(outer, s.n_btiles * TB, b0);
+  const T* auxb = REDUCE ? reinterpret_cast<const T*>(s.aux + vb_out) : nullptr;
   R avp[PRE_AUX ? PER : 1];
   T fpre[PRELOAD ? PER : 1][CW];
   if constexpr (PRELOAD) {
@@ -808,9 +839,7 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
       const int q = threadIdx.x + c * NT;
       if (ITEMS % NT == 0 || q < ITEMS) {
         const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-        if constexpr (PRE_AUX)
-          avp[c] = ld16x<NTA>(reinterpret_cast<const T*>(
-              s.aux + rhs * s.out_rhs + vec_off<N>(outer, s.n_btiles * TB, b0 + b, i)));
+        if constexpr (PRE_AUX) avp[c] = ld16x<NTA>(at_bytes(auxb, vec_in_bytes<T, N>(b, i)));
         int kzp[CW];
         bool dcp[CW];
         split_facs<T, N, CW>(fac_r, s, outer, b0 + b, i, fpre[c], kzp, dcp);
@@ -894,13 +923,13 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
         const int q = threadIdx.x + c * NT;
         if (ITEMS % NT == 0 || q < ITEMS) {
           const int i = q / (TB / CW), b = (q - i * (TB / CW)) * CW;
-          const int64_t off = ob + vec_off<N>(outer, ncols, b0 + b, i);
+          const uint32_t vo = vec_in_bytes<T, N>(b, i);
           const R v = *reinterpret_cast<const R*>(lds + q * CW);
           R av{};
           if constexpr (PRE_AUX) {
             av = avp[c];
           } else if constexpr (REDUCE && MODE != SM_FWD_CGQF) {
-            av = ld16x<NTA>(reinterpret_cast<const T*>(s.aux + off));
+            av = ld16x<NTA>(at_bytes(auxb, vo));
           }
           T f[CW];
           int kz[CW];
@@ -910,7 +939,8 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
 #pragma unroll
             for (int j = 0; j < CW; ++j)
               if (dc[j]) {
-                const cplx<T> p0 = s.aux[off + j];
+                const cplx<T> p0 =
+                    *reinterpret_cast<const cplx<T>*>(at_bytes(auxb, vo + j * (uint32_t)sizeof(V)));
                 av[2 * j] = p0.x;
                 av[2 * j + 1] = p0.y;
               }
@@ -923,13 +953,13 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
 #pragma unroll
           for (int j = 0; j < CW; ++j) {
             cplx<double> bv{0.0, 0.0};
-            if constexpr (MODE == SM_FWD_RES) bv = s.bvec[off + j];
+            if constexpr (MODE == SM_FWD_RES) bv = s.bvec[vb_out + vo / sizeof(V) + j];
             const cplx<T> r = split_out<T, N, MODE>(f[j], kz[j], dc[j], V{v[2 * j], v[2 * j + 1]},
                                                     V{av[2 * j], av[2 * j + 1]}, bv, acc, acc2);
             o[2 * j] = r.x;
             o[2 * j + 1] = r.y;
           }
-          st16x<NTA>(reinterpret_cast<T*>(s.out + off), o);
+          st16x<NTA>(at_bytes(reinterpret_cast<T*>(s.out + vb_out), vo), o);
         }
       }
     } else {
