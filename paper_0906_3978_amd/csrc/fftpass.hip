@@ -1033,17 +1033,23 @@ __global__ __launch_bounds__(NTS, strided_waves<NTS>()) void k_strided(StrArgs<T
 // finalize: sum the block partials of one reduction per RHS (fixed order)
 // and update the scalar CG state
 // ---------------------------------------------------------------------------
+// The finalize kernels run one block per RHS.  Their sums of block partials
+// (tens of thousands, in L2) are bound by load round trips: each thread keeps
+// eight independent loads in flight per round, summed in a fixed order.
+constexpr int FIN_THREADS = 1024;
 __device__ __forceinline__ double sum_parts(const double* p, int nparts, double* red) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  constexpr int U = 8;
+  double s[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) s[u] = 0.0;
   int i = threadIdx.x;
-  for (; i + 768 < nparts; i += 1024) {
-    s0 += p[i];
-    s1 += p[i + 256];
-    s2 += p[i + 512];
-    s3 += p[i + 768];
+  for (; i + (U - 1) * FIN_THREADS < nparts; i += U * FIN_THREADS) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] += p[i + u * FIN_THREADS];
   }
-  for (; i < nparts; i += 256) s0 += p[i];
-  return block_sum((s0 + s1) + (s2 + s3), red);
+  for (; i < nparts; i += FIN_THREADS) s[0] += p[i];
+  const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  return block_sum(t, red);
 }
 
 // Iteration bookkeeping and stopping once the new recursive residual r.r is
@@ -1076,9 +1082,9 @@ __device__ __forceinline__ void count_iteration(CgState* st, double rho_new) {
 }
 
 template <int KIND>
-__global__ __launch_bounds__(256) void k_finalize(const double* partials, int nparts, int skip,
-                                                  CgState* st_all) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* partials, int nparts,
+                                                          int skip, CgState* st_all) {
+  __shared__ double red[FIN_THREADS / 64];
   const int rhs = blockIdx.x;
   CgState* st = st_all + rhs;
   if (skip_rhs(st, skip)) return;
@@ -1126,11 +1132,11 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partials, int np
 // Folded iteration, after FWD_CGQF: p.q and q.q from p.p (FIN_RRF), the z
 // middle pass's sums of nbar w u^2 and FWD_CGQF's q'.q' and monopole term;
 // alpha, and beta from the recurrence.
-__global__ __launch_bounds__(256) void k_finalize_fold_pq(const double* part_z, int nzb,
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize_fold_pq(const double* part_z, int nzb,
                                                           const double* part_x, int nxb,
                                                           double m_cells, int skip,
                                                           CgState* st_all) {
-  __shared__ double red[4];
+  __shared__ double red[FIN_THREADS / 64];
   const int rhs = blockIdx.x;
   CgState* st = st_all + rhs;
   if (skip_rhs(st, skip)) return;
@@ -1166,8 +1172,8 @@ __global__ __launch_bounds__(256) void k_finalize_fold_pq(const double* part_z, 
 hipError_t launch_finalize_fold_pq(const double* part_z, int nzb, const double* part_x, int nxb,
                                    double m_cells, int skip, CgState* st, int nrhs,
                                    hipStream_t s) {
-  klaunch(k_finalize_fold_pq, dim3(nrhs), dim3(256), 0, s, part_z, nzb, part_x, nxb, m_cells, skip,
-          st);
+  klaunch(k_finalize_fold_pq, dim3(nrhs), dim3(FIN_THREADS), 0, s, part_z, nzb, part_x, nxb,
+          m_cells, skip, st);
   return hipGetLastError();
 }
 
@@ -1175,16 +1181,16 @@ hipError_t launch_finalize(int kind, const double* partials, int nparts, int ski
                            int nrhs, hipStream_t s) {
   switch (kind) {
     case FIN_PQ:
-      klaunch(k_finalize<FIN_PQ>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      klaunch(k_finalize<FIN_PQ>, dim3(nrhs), dim3(FIN_THREADS), 0, s, partials, nparts, skip, st);
       break;
     case FIN_RR:
-      klaunch(k_finalize<FIN_RR>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      klaunch(k_finalize<FIN_RR>, dim3(nrhs), dim3(FIN_THREADS), 0, s, partials, nparts, skip, st);
       break;
     case FIN_RES:
-      klaunch(k_finalize<FIN_RES>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      klaunch(k_finalize<FIN_RES>, dim3(nrhs), dim3(FIN_THREADS), 0, s, partials, nparts, skip, st);
       break;
     case FIN_RRF:
-      klaunch(k_finalize<FIN_RRF>, dim3(nrhs), dim3(256), 0, s, partials, nparts, skip, st);
+      klaunch(k_finalize<FIN_RRF>, dim3(nrhs), dim3(FIN_THREADS), 0, s, partials, nparts, skip, st);
       break;
     default: return hipErrorInvalidValue;
   }
