@@ -507,7 +507,8 @@ def post_run(ctx, wl, field, reps=3):
            "compare_ms": round(1e3 * t_cmp, 3), "compare_gbs": gbs(cmp_b, t_cmp),
            "filter_bytes_per_cell": 80,
            "moments_smoothed_masked": [round(x, 6) for x in mom],
-           "measures_wf_vs_iw_rs5": [round(x, 6) for x in cmp_]}
+           # D_KL is undefined (NaN) where 1 + delta <= 0: null in the JSON line
+           "measures_wf_vs_iw_rs5": [round(x, 6) if math.isfinite(x) else None for x in cmp_]}
     log(f"[post] {res}")
     return res
 
