@@ -121,6 +121,25 @@ def test_deposit_order_independent(ctx):
     assert int(g1.sum()) == len(xyz) << 39
 
 
+@pytest.mark.parametrize("scheme", ["cic", "tsc"])
+def test_deposit_piled_on_one_point(ctx, scheme):
+    """The degenerate catalogue of the contention measurement: 200 000
+    galaxies at one position, every one of them adding to the same 8 or 27
+    fine nodes.  Integer atomics make the grid exact whatever the order in
+    which the adds land: equal to the oracle's, total N_gal 2^39."""
+    n, box, ngal = 32, 100.0, 200_000
+    p = 0.5 * box + 0.3 * box / (2 * n)
+    xyz = np.full((ngal, 3), p)
+    ctx.set_grid(n, box)
+    ctx.set_mask(np.ones((n, n, n)))
+    ctx.set_galaxies(xyz)
+    ctx.deposit(scheme, 2)
+    fine, _, _ = ctx.get_deposit(True, False, 2)
+    assert np.array_equal(fine, od.deposit(xyz, 2 * n, box, scheme))
+    assert int(fine.sum()) == ngal << 39
+    assert np.count_nonzero(fine) == (8 if scheme == "cic" else 27)
+
+
 def test_supersample_after_a_larger_grid(ctx):
     """One context reused from a larger to smaller grids: the fine-grid FFT
     tables follow the grid (a 48^3 fine grid after a 64^3 one once kept the
