@@ -52,6 +52,10 @@ template <typename T, int N> constexpr int z_nb() {
   int lim = elems / N;
   if (lim < 1) lim = 1;
   const int pairs = N * N / 2;
+  // small grids: fewer pencils per block, so that a pass still spreads over
+  // at least 512 blocks (two per CU) where the grid has that many pairs; a
+  // 32^3 grid otherwise ran its z passes on 8 blocks
+  if (pairs / 512 < lim) lim = pairs / 512 > 1 ? pairs / 512 : 1;
   for (int d = lim; d >= 1; --d)
     if (pairs % d == 0) return d;
   return 1;
